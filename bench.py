@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Barnes-Hut hot-path benchmark on one MI355X.
+
+Workload (default): Plummer sphere, N = 2^20, seed 2, eps = 0.005, theta = 0.5,
+leaf_cap = 1, kick-drift-kick steps with dt = 1e-4 and a full tree rebuild
+every step.  A step is one pass of the whole hot path: bbox, Morton keys,
+radix sort, octree, upward pass, force walk, kicks and drift.
+
+Prints ONE JSON line.  `value` is force evaluations per second in Mparticles/s
+for the FP32 mode, counted over whole steps (N / step time: every step is one
+complete force evaluation from positions, tree included); the FP64 mode is
+reported beside it.  The walk kernel's own time, measured with events on the
+stream it runs on, gives the roofline entry; the oracle timed on the host gives
+the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "BH force-evals Mparticles/s at theta=0.5, N=1M (FP32 vs FP64); served p99 latency"
+FP32_PEAK = 157.3e12     # MI355X vector FP32 (packed issue)
+FP64_PEAK = 78.6e12      # MI355X vector FP64
+FLOPS_PER_INTERACTION = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--eps", type=float, default=0.005)
+    ap.add_argument("--dt", type=float, default=1e-4)
+    ap.add_argument("--leaf-cap", type=int, default=1)
+    ap.add_argument("--walk-reps", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=262144, help="oracle walk targets for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precisions", default="fp32,fp64")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import icgen
+    import paper_1109_5190_amd as bh
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = icgen.plummer(a.n, a.seed)
+    print(f"# generated {a.n} Plummer particles in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    pos0 = torch.tensor(s.pos, device=dev)
+    vel0 = torch.tensor(s.vel, device=dev)
+    mass = torch.tensor(s.mass, device=dev)
+    ctx = bh.Context(0)
+    stream = torch.cuda.current_stream(dev)
+
+    results = {}
+    for prec in a.precisions.split(","):
+        p = bh.params(a.theta, a.eps, 1.0, a.leaf_cap, prec)
+        # ---- full steps (the headline) ----
+        pos = pos0.clone()
+        vel = vel0.clone()
+        sim = bh.Sim(ctx, pos, vel, mass, p)
+        sim.step(a.warmup, a.dt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(a.steps, a.dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / max(a.steps, 1)
+        # ---- the walk kernel alone, on a tree at the initial positions ----
+        tree = bh.Tree(ctx, pos0, mass, p).upward()
+        tree.forces()
+        torch.cuda.synchronize()
+        w0 = torch.cuda.Event(enable_timing=True)
+        w1 = torch.cuda.Event(enable_timing=True)
+        w0.record(stream)
+        for _ in range(a.walk_reps):
+            acc = tree.forces()
+        w1.record(stream)
+        torch.cuda.synchronize()
+        ms_walk = w0.elapsed_time(w1) / a.walk_reps
+        # ---- build + upward alone ----
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record(stream)
+        t2 = bh.Tree(ctx, pos0, mass, p).upward()
+        b1.record(stream)
+        torch.cuda.synchronize()
+        ms_build = b0.elapsed_time(b1)
+        del t2
+        st = tree.forces_stats()
+        torch.cuda.synchronize()
+        tot = st["totals"]
+        inter = int(tot["n_mono"] + tot["n_p2p"])
+        results[prec] = dict(ms_per_step=ms_step, ms_walk=ms_walk, ms_build_upward=ms_build,
+                             interactions=inter, visits=int(tot["n_visits"]), fallbacks=int(tot["n_fallback"]),
+                             acc=st["acc"].cpu().numpy())
+        print(f"# {prec}: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, build+upward {ms_build:.3f} ms, "
+              f"{inter / a.n:.1f} interactions/particle", file=sys.stderr, flush=True)
+        del sim, tree
+
+    head = "fp32" if "fp32" in results else next(iter(results))
+    r = results[head]
+    peak = FP32_PEAK if head == "fp32" else FP64_PEAK
+    achieved = FLOPS_PER_INTERACTION * r["interactions"] / (r["ms_walk"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": a.n / (r["ms_per_step"] * 1e-3) / 1e6,
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Plummer sphere N={a.n} seed={a.seed} eps={a.eps} theta={a.theta} "
+                               f"leaf_cap={a.leaf_cap}, KDK dt={a.dt} with tree rebuild every step",
+                   "n": a.n, "theta": a.theta, "eps": a.eps, "leaf_cap": a.leaf_cap, "dt": a.dt},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"k_walk32 ({FLOPS_PER_INTERACTION} flops x {r['interactions']} interactions "
+                               f"per launch / {r['ms_walk']:.3f} ms)"},
+        "walk_only": {"ms": r["ms_walk"], "mparticles_per_s": a.n / (r["ms_walk"] * 1e-3) / 1e6,
+                      "interactions_per_particle": r["interactions"] / a.n,
+                      "fp64_fallback_tests": r["fallbacks"], "opening_tests": r["visits"]},
+        "build_upward_ms": r["ms_build_upward"],
+    }
+    for prec, rr in results.items():
+        if prec == head:
+            continue
+        pk = FP64_PEAK if prec == "fp64" else FP32_PEAK
+        ach = FLOPS_PER_INTERACTION * rr["interactions"] / (rr["ms_walk"] * 1e-3)
+        out[prec] = {"value": a.n / (rr["ms_per_step"] * 1e-3) / 1e6, "unit": "Mparticles/s",
+                     "ms_per_step": rr["ms_per_step"], "walk_ms": rr["ms_walk"],
+                     "build_upward_ms": rr["ms_build_upward"],
+                     "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s",
+                                  "frac": ach / pk}}
+
+    if not a.no_cpu:
+        import oracle
+        ns = min(a.cpu_sample, a.n)
+        rng = np.random.default_rng(0)
+        targets = np.sort(rng.choice(a.n, size=ns, replace=False)).astype(np.int64)
+        cores = len(os.sched_getaffinity(0))
+        c0 = time.time()
+        T = oracle.Tree(s.pos, s.mass, a.leaf_cap)
+        c1 = time.time()
+        ref = T.walk(a.theta, a.eps, 1.0, targets, nthreads=cores)
+        c2 = time.time()
+        t_full = (c1 - c0) + (c2 - c1) * a.n / ns
+        out["cpu_baseline"] = {"value": a.n / t_full / 1e6, "unit": "Mparticles/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"full FP64 tree build (1 thread, {c1 - c0:.2f}s) + walk of {ns} random "
+                                         f"targets on {cores} threads ({c2 - c1:.2f}s), walk time scaled to N"}
+        errs = {}
+        for prec, rr in results.items():
+            acc = rr["acc"][targets]
+            num = np.sqrt(((acc - ref["acc"]) ** 2).sum() / (ref["acc"] ** 2).sum())
+            mx = (np.linalg.norm(acc - ref["acc"], axis=1) / np.linalg.norm(ref["acc"], axis=1)).max()
+            errs[prec] = {"rms_rel": float(num), "max_rel": float(mx)}
+        out["force_error_vs_oracle"] = dict(errs, sample=f"{ns} random targets at the initial positions")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * bh.h -- C ABI of the MI355X Barnes-Hut library (libbh.so).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the hot path of
+ * the Barnes-Hut N-body method as described in "Improving the scalability of
+ * parallel N-body applications with an event driven constraint based
+ * execution model" (Dekate et al.):
+ *   - the cube hierarchy: recursive subdivision of a root cube until a cube
+ *     holds at most `leaf_cap` particles (section 1, introduction; Fig. 2);
+ *   - the centre of mass of every cube (section 1);
+ *   - the force on every body, where a cube is treated as one body only when
+ *     its distance D from the body exceeds r/theta (section 3, first
+ *     paragraph and Fig. 1), with r the cube side and D the distance to the
+ *     cube's centre of mass; the test is strict and evaluated per body;
+ *   - iterations: a new tree every step (section 1, load-balancing item;
+ *     section 3, global barrier at tree construction), advanced with
+ *     kick-drift-kick leapfrog.
+ * Readings of points the paper leaves open (root cube, depth limit 21,
+ * removal of single-child cubes, Plummer softening, self-exclusion) are the
+ * same as in the oracle and are listed in the repository's design notes.
+ *
+ * Conventions for every entry point:
+ *  - Return value: bh_status.  No exception or abort crosses the ABI.  On an
+ *    error, bh_last_error() returns a thread-local message, valid until the
+ *    next call on the same thread.
+ *  - Memory: the CALLER owns all device memory: inputs, outputs, workspaces
+ *    and the server arena.  The library sub-allocates inside the workspace it
+ *    is given and never frees caller memory.  Handles (bh_ctx, bh_tree,
+ *    bh_sim, bh_forest, bh_server) are small host objects.
+ *  - Ordering: calls are asynchronous on the context's HIP stream; a call
+ *    returns once its work is enqueued.  Outputs are valid after the stream
+ *    is synchronised (bh_ctx_sync).  Calls marked SYNC synchronise the stream
+ *    themselves.
+ *  - Layouts: positions, velocities and accelerations are row-major (n, 3)
+ *    FP64 arrays in device memory in the caller's particle order; masses are
+ *    (n,) FP64.  Results come back in the caller's order.
+ *  - Sizes: 1 <= n <= 2^30 - 1 per call (per forest: the sum).
+ */
+#ifndef BH_H
+#define BH_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BH_OK = 0,
+    BH_E_INVAL = 1,      /* bad argument (null pointer, n < 1, theta < 0, eps < 0, leaf_cap not in [1,64], non-finite) */
+    BH_E_NOMEM = 2,      /* workspace / arena too small, or a request that can never fit */
+    BH_E_DEVICE = 3,     /* HIP error, or a device-side fault flag (non-finite state) */
+    BH_E_BUSY = 4,       /* request not finished yet */
+    BH_E_NOTFOUND = 5,   /* unknown request id */
+    BH_E_OVERFLOW = 6,   /* walk stack overflow (cannot happen for depth <= 21; reported if it does) */
+    BH_E_CANCELLED = 7   /* request was cancelled */
+} bh_status;
+
+typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
+
+/* Method parameters.
+ *  theta     opening parameter (>= 0); theta = 0 reduces the walk to direct summation.
+ *  eps       Plummer softening length (>= 0): pair kernel G m d / (|d|^2 + eps^2)^(3/2).
+ *  G         gravitational constant.
+ *  leaf_cap  a cube holding at most leaf_cap particles is a leaf (the paper uses 1); 1..64.
+ *  precision BH_FP64: all walk arithmetic in FP64.
+ *            BH_FP32: pair/monopole arithmetic in FP32 with compensated accumulation;
+ *            opening decisions are certified against the FP64 test (re-evaluated in
+ *            FP64 when the FP32 value is within its rounding bound of the threshold),
+ *            so the interaction sets are those of the FP64 method.
+ *  flags     reserved, pass 0. */
+typedef struct {
+    double theta, eps, G;
+    int32_t leaf_cap;
+    int32_t precision;
+    uint32_t flags;
+    uint32_t reserved;
+} bh_params;
+
+/* Interaction totals of one force evaluation (filled by the *_stats calls, SYNC). */
+typedef struct {
+    uint64_t n_mono;      /* accepted cubes (monopole interactions) summed over bodies */
+    uint64_t n_p2p;       /* body-body interactions in opened leaves, self excluded */
+    uint64_t n_visits;    /* (cube, body) opening tests */
+    uint64_t n_fallback;  /* FP32 opening tests re-evaluated in FP64 */
+} bh_stats;
+
+typedef struct bh_ctx bh_ctx;
+typedef struct bh_tree bh_tree;
+typedef struct bh_sim bh_sim;
+typedef struct bh_forest bh_forest;
+typedef struct bh_server bh_server;
+
+/* ---------------------------------------------------------------- context --- */
+
+/* Context bound to HIP device `device` and stream `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  The stream is not owned. */
+bh_status bh_ctx_create(int device, void *hip_stream, bh_ctx **out);
+bh_status bh_ctx_destroy(bh_ctx *ctx);
+/* SYNC: waits for the stream and reports a pending device-side fault flag. */
+bh_status bh_ctx_sync(bh_ctx *ctx);
+const char *bh_last_error(void);
+/* Library version string, e.g. "bh-mi355x 0.1". */
+const char *bh_version(void);
+
+/* ------------------------------------------------------------ single tree --- */
+
+/* Bytes of device workspace needed by bh_build for n particles. */
+size_t bh_workspace_bytes(int64_t n, const bh_params *p);
+
+/* Octree construction (paper section 1; Fig. 2): root cube, 63-bit Morton
+ * keys, stable radix sort, canonical compressed octree.  pos (n x 3) and
+ * mass (n) are device pointers that must stay valid and unchanged until the
+ * tree is freed.  ws: device workspace of ws_bytes >= bh_workspace_bytes.
+ * *out receives a host handle. */
+bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                   const bh_params *p, void *ws, size_t ws_bytes, bh_tree **out);
+
+/* Upward pass (section 1: centre of mass of each cube): FP64 mass and centre
+ * of mass of every node, summed in a fixed order (particles in key order at
+ * leaves, children in octant order above), and the walk records. */
+bh_status bh_upward(bh_ctx *ctx, bh_tree *tree);
+
+/* Force walk (section 3: opening criterion; force stage): acc (n x 3 FP64,
+ * device, caller's order) receives G * sum m d / (|d|^2+eps^2)^(3/2) over the
+ * accepted cubes and the leaf pairs; pot (nullable, n FP64 device) the
+ * potential -G sum m / sqrt(|d|^2+eps^2) over the same set. */
+bh_status bh_forces(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot);
+
+/* As bh_forces, plus per-body interaction counts and set checksum (device
+ * arrays of n, caller's order; each nullable) and the totals (SYNC).  The
+ * checksum of body i is the sum mod 2^64 of mix64(node) over accepted cubes
+ * and mix64(n_nodes + j) over pair partners j, with node the preorder index
+ * and mix64 the SplitMix64 finalizer of x + 0x9e3779b97f4a7c15. */
+bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, int64_t *n_mono,
+                          int64_t *n_p2p, uint64_t *hash, bh_stats *totals);
+
+/* SYNC.  Number of tree nodes and the root cube (lo[3] host, k: side 2^k). */
+bh_status bh_tree_info(bh_ctx *ctx, bh_tree *tree, int64_t *n_nodes, double lo[3], int32_t *k);
+
+/* Canonical export (device pointers, each nullable): sorted keys (n), order
+ * perm (n, perm[r] = original index of rank r), and per node in depth-first
+ * preorder with children in ascending octant order: level, first rank, count,
+ * parent (-1 for the root), mass M and centre of mass com (n_nodes x 3).
+ * Node arrays must hold bh_tree_info's n_nodes entries. */
+bh_status bh_tree_export(bh_ctx *ctx, bh_tree *tree, uint64_t *keys, uint32_t *perm, int32_t *level,
+                         uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com);
+
+bh_status bh_tree_free(bh_ctx *ctx, bh_tree *tree);
+
+/* -------------------------------------------------------------- simulation --- */
+
+/* A simulation views caller memory: pos, vel, acc (n x 3) are updated in place,
+ * mass (n) is read.  acc is computed by the first bh_step. */
+size_t bh_sim_workspace_bytes(int64_t n, const bh_params *p);
+bh_status bh_sim_create(bh_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double *acc,
+                        const bh_params *p, void *ws, size_t ws_bytes, bh_sim **out);
+/* nsteps kick-drift-kick steps with a full tree rebuild each step:
+ * v += (dt/2) a; x += dt v; rebuild, upward, walk; v += (dt/2) a. */
+bh_status bh_step(bh_ctx *ctx, bh_sim *sim, int32_t nsteps, double dt);
+/* SYNC.  out_KW = {K, W}: K = 1/2 sum m |v|^2, W = 1/2 sum m phi, phi from a
+ * walk at the current positions (FP64 reductions). */
+bh_status bh_energy(bh_ctx *ctx, bh_sim *sim, double out_KW[2]);
+bh_status bh_sim_destroy(bh_ctx *ctx, bh_sim *sim);
+
+/* ------------------------------------------------------------------ forest --- */
+
+/* Many independent simulations advanced together: their particles are
+ * concatenated (simulation s owns rows [off_s, off_s + n[s]) of pos, vel,
+ * acc and mass, off_s = n[0] + ... + n[s-1]); every kernel of a step covers
+ * all of them in one launch. */
+size_t bh_forest_workspace_bytes(int32_t n_sims, const int64_t *n, const bh_params *per_sim);
+bh_status bh_forest_create(bh_ctx *ctx, int32_t n_sims, const int64_t *n, const bh_params *per_sim,
+                           double *pos, double *vel, const double *mass, double *acc, void *ws,
+                           size_t ws_bytes, bh_forest **out);
+/* dt: host array of n_sims time steps. */
+bh_status bh_forest_step(bh_ctx *ctx, bh_forest *f, int32_t nsteps, const double *dt);
+/* Forces at the current positions into acc (and pot, nullable, concatenated). */
+bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *f, double *pot);
+/* Record one step of the forest as a HIP graph (on first call) and replay it
+ * nsteps times. */
+bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *f, int32_t nsteps, const double *dt);
+/* SYNC.  Per-simulation energies at the current positions: out_KW[2 s] = K_s,
+ * out_KW[2 s + 1] = W_s (host array of 2 n_sims); also refreshes acc. */
+bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *f, double *out_KW);
+bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *f);
+
+/* ----------------------------------------------------- initial conditions --- */
+
+/* Device-side generation of the same inputs as the host generator: Philox4x32-10
+ * keyed by seed, counter (i_lo, i_hi, call, tag).  kind 0: Plummer sphere by
+ * Aarseth-Henon-Wielen with scale radius a, total mass M, mass-fraction cut
+ * 0.999, shifted to its centre-of-mass frame; kind 1: uniform cube [-a, a]^3,
+ * masses uniform in [0.5, 1.5] M / n, at rest.  pos, vel (n x 3), mass (n). */
+bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M,
+                         double *pos, double *vel, double *mass);
+
+/* ---------------------------------------------------------------- serving --- */
+
+typedef struct {
+    int64_t n;          /* particles */
+    int32_t steps;      /* KDK steps */
+    int32_t ic_kind;    /* 0 Plummer, 1 uniform cube */
+    uint64_t seed;
+    bh_params p;
+    double dt;
+} bh_request;
+
+typedef struct {
+    int32_t state;       /* 0 queued, 1 running, 2 done, 3 failed, 4 cancelled */
+    int32_t steps_done;
+    double t_submit, t_admit, t_done;   /* seconds on the server's monotonic clock */
+    double K, W;         /* energies at completion */
+} bh_result;
+
+/* A continuous-batching server: its own host thread and HIP stream on ctx's
+ * device; requests are admitted first-come first-served while their device
+ * footprint fits the caller's arena (device memory, arena_bytes) and the slot
+ * and resident-particle caps; every iteration advances all resident
+ * simulations by one step in one forest launch sequence; finished ones retire
+ * and free their arena space for the next. */
+bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_slots,
+                           int64_t max_resident_particles, bh_server **out);
+/* BH_E_NOMEM if the request can never fit the arena or the caps. */
+bh_status bh_server_submit(bh_server *s, const bh_request *req, uint64_t *id);
+/* Thread-safe.  BH_E_BUSY while queued or running (res is still filled). */
+bh_status bh_server_poll(bh_server *s, uint64_t id, bh_result *res);
+/* Copy a finished request's final state into caller device memory (n x 3
+ * each, nullable) and release it. */
+bh_status bh_server_fetch(bh_server *s, uint64_t id, double *pos, double *vel);
+bh_status bh_server_cancel(bh_server *s, uint64_t id);
+/* Seconds on the server clock (same clock as bh_result times). */
+double bh_server_now(bh_server *s);
+/* Drains running requests, stops the thread. */
+bh_status bh_server_destroy(bh_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BH_H */

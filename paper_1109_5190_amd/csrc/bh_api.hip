@@ -1,0 +1,553 @@
+// C ABI of libbh.so: contexts, workspace planning, trees, simulations and
+// forests.  Every entry point validates its arguments, enqueues kernels on the
+// context's stream and returns a bh_status; no exception crosses the ABI.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bh.h"
+#include "bh_common.h"
+#include "bh_internal.h"
+
+using namespace bh;
+
+static thread_local std::string g_err;
+
+bh_status bh_fail(bh_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) return bh_fail(BH_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------- validation ---
+
+bh_status bh_check_params(const bh_params *p) {
+    if (!p) return bh_fail(BH_E_INVAL, "params is NULL");
+    if (!std::isfinite(p->theta) || p->theta < 0.0) return bh_fail(BH_E_INVAL, "theta must be finite and >= 0");
+    if (!std::isfinite(p->eps) || p->eps < 0.0) return bh_fail(BH_E_INVAL, "eps must be finite and >= 0");
+    if (!std::isfinite(p->G)) return bh_fail(BH_E_INVAL, "G must be finite");
+    if (p->leaf_cap < 1 || p->leaf_cap > 64) return bh_fail(BH_E_INVAL, "leaf_cap must be in [1, 64]");
+    if (p->precision != BH_FP64 && p->precision != BH_FP32) return bh_fail(BH_E_INVAL, "precision must be BH_FP64 or BH_FP32");
+    return BH_OK;
+}
+
+// ------------------------------------------------------------- planning ---
+
+namespace {
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+// Lays out a forest in `ws` (or only measures it when ws == NULL).  Returns the bytes needed.
+size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws) {
+    F.seg.assign(nseg, SegDesc{});
+    F.tiles.clear();
+    F.groups.clear();
+    uint64_t ntot = 0;
+    for (int32_t s = 0; s < nseg; ++s) {
+        SegDesc &d = F.seg[s];
+        d.start = (uint32_t)ntot;
+        d.n = (uint32_t)n[s];
+        d.tile_base = (uint32_t)F.tiles.size();
+        d.ntiles = (uint32_t)((n[s] + kTile - 1) / kTile);
+        d.group_base = (uint32_t)F.groups.size();
+        d.ngroups = (uint32_t)((n[s] + kGroup - 1) / kGroup);
+        d.leaf_cap = p[s].leaf_cap;
+        d.precision = p[s].precision;
+        d.theta = p[s].theta;
+        d.eps = p[s].eps;
+        d.G = p[s].G;
+        d.dt = 0.0;
+        for (uint32_t t = 0; t < d.ntiles; ++t) {
+            uint32_t st = d.start + t * kTile;
+            uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);
+            F.tiles.push_back(TileDesc{st, c, (uint32_t)s, 0});
+        }
+        for (uint32_t g = 0; g < d.ngroups; ++g) {
+            uint32_t st = d.start + g * kGroup;
+            uint32_t c = (uint32_t)std::min<int64_t>(kGroup, n[s] - (int64_t)g * kGroup);
+            F.groups.push_back(GroupDesc{st, c, (uint32_t)s, 0});
+        }
+        ntot += (uint64_t)n[s];
+    }
+    F.precision = p[0].precision;
+    ForestDev &D = F.dev;
+    D = ForestDev{};
+    D.nseg = (uint32_t)nseg;
+    D.ntot = (uint32_t)ntot;
+    D.ntiles = (uint32_t)F.tiles.size();
+    D.ngroups = (uint32_t)F.groups.size();
+    D.mcap = (uint32_t)(2 * ntot);
+    const size_t N = ntot, Mc = D.mcap;
+    size_t scan_len = std::max<size_t>(std::max<size_t>(256 * (size_t)D.ntiles, N), Mc);
+    Carver c{ws};
+    D.seg = c.take<SegDesc>(nseg);
+    D.st = c.take<SegState>(nseg);
+    D.tiles = c.take<TileDesc>(D.ntiles);
+    D.groups = c.take<GroupDesc>(D.ngroups);
+    D.segid = c.take<uint32_t>(N);
+    D.keys = c.take<uint64_t>(N);
+    D.keys_alt = c.take<uint64_t>(N);
+    D.idx = c.take<uint32_t>(N);
+    D.idx_alt = c.take<uint32_t>(N);
+    D.cnt = c.take<uint32_t>(256 * (size_t)D.ntiles + 1);
+    D.scan_tmp = c.take<uint32_t>(scan_len / 2048 + 2);
+    D.spos = c.take<double>(3 * N);
+    D.smass = c.take<double>(N);
+    D.lcp = c.take<int8_t>(N + 1);
+    D.mask = c.take<uint32_t>(N);
+    D.base = c.take<uint32_t>(N + 1);
+    D.nlevel = c.take<uint8_t>(Mc);
+    D.nchild = c.take<uint32_t>(Mc + 1);
+    D.nfirst = c.take<uint32_t>(Mc);
+    D.ncount = c.take<uint32_t>(Mc);
+    D.nparent = c.take<uint32_t>(Mc);
+    D.ncrank = c.take<uint32_t>(Mc);
+    D.cs = c.take<uint32_t>(Mc + 1);
+    D.slot_of = c.take<uint32_t>(Mc);
+    D.node_at_slot = c.take<uint32_t>(Mc);
+    D.level_cnt = c.take<uint32_t>(32);
+    D.level_off = c.take<uint32_t>(32);
+    D.level_cur = c.take<uint32_t>(32);
+    D.level_list = c.take<uint32_t>(N + 1);
+    D.nM = c.take<double>(Mc);
+    D.nS = c.take<double>(3 * Mc);
+    bool any32 = false, any64 = false;
+    for (int32_t s = 0; s < nseg; ++s) (p[s].precision == BH_FP32 ? any32 : any64) = true;
+    D.w32 = any32 ? c.take<WRec32>(Mc) : nullptr;
+    D.w64 = any64 ? c.take<WRec64>(Mc) : nullptr;
+    D.err = c.take<uint32_t>(64);
+    D.stats = c.take<unsigned long long>(8);
+    D.red = c.take<double>(2 * (size_t)nseg);
+    D.pot = c.take<double>(N);
+    F.ws = ws;
+    F.ws_bytes = c.off + 256;
+    return c.off + 256;
+}
+
+static bh_status validate_sizes(int32_t nseg, const int64_t *n, const bh_params *p) {
+    if (nseg < 1) return bh_fail(BH_E_INVAL, "need at least one simulation");
+    if (!n || !p) return bh_fail(BH_E_INVAL, "NULL size or params array");
+    int64_t tot = 0;
+    for (int32_t s = 0; s < nseg; ++s) {
+        if (n[s] < 1) return bh_fail(BH_E_INVAL, "every simulation needs n >= 1");
+        bh_status st = bh_check_params(&p[s]);
+        if (st != BH_OK) return st;
+        if (p[s].precision != p[0].precision) return bh_fail(BH_E_INVAL, "all simulations of a forest share one precision");
+        tot += n[s];
+        if (tot > (int64_t)0x3fffffff) return bh_fail(BH_E_INVAL, "too many particles (limit 2^30 - 1 per call)");
+    }
+    return BH_OK;
+}
+
+bh_status bh_forest_init(bh_ctx *ctx, ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, void *ws,
+                         size_t ws_bytes) {
+    if (!ws) return bh_fail(BH_E_INVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return bh_fail(BH_E_INVAL, "workspace must be 256-byte aligned");
+    size_t need = bh_plan_forest(F, nseg, n, p, nullptr);
+    if (ws_bytes < need) return bh_fail(BH_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    bh_plan_forest(F, nseg, n, p, (char *)ws);
+    F.ctx = ctx;
+    hipStream_t s = ctx->stream;
+    ForestDev &D = F.dev;
+    HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
+    if (!F.tiles.empty())
+        HIPCHK(hipMemcpyAsync(D.tiles, F.tiles.data(), sizeof(TileDesc) * F.tiles.size(), hipMemcpyHostToDevice, s));
+    if (!F.groups.empty())
+        HIPCHK(hipMemcpyAsync(D.groups, F.groups.data(), sizeof(GroupDesc) * F.groups.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_fill_u32(D.err, 0, 64, s));
+    HIPCHK(launch_fill_u32((uint32_t *)D.stats, 0, 16, s));
+    HIPCHK(launch_segid(D, s));
+    return BH_OK;
+}
+
+bh_status bh_forest_upload_seg(ForestHost &F) {
+    HIPCHK(hipMemcpyAsync(F.dev.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice,
+                          F.ctx->stream));
+    // keep the host table alive until the copy has been consumed
+    HIPCHK(hipStreamSynchronize(F.ctx->stream));
+    return BH_OK;
+}
+
+bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot) {
+    hipStream_t s = F.ctx->stream;
+    HIPCHK(launch_build(F.dev, pos, mass, s));
+    HIPCHK(launch_upward(F.dev, s));
+    HIPCHK(launch_walk(F.dev, F.precision, false, acc, pot, nullptr, nullptr, nullptr, s));
+    return BH_OK;
+}
+
+bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc) {
+    hipStream_t s = F.ctx->stream;
+    HIPCHK(launch_kick(F.dev, vel, acc, 0.5, s));
+    HIPCHK(launch_drift(F.dev, pos, vel, s));
+    bh_status st = bh_forest_eval(F, pos, mass, acc, nullptr);
+    if (st != BH_OK) return st;
+    HIPCHK(launch_kick(F.dev, vel, acc, 0.5, s));
+    return BH_OK;
+}
+
+bh_status bh_forest_check_err(ForestHost &F) {
+    uint32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, F.dev.err, sizeof(uint32_t), hipMemcpyDeviceToHost, F.ctx->stream));
+    HIPCHK(hipStreamSynchronize(F.ctx->stream));
+    if (e & kErrStack) return bh_fail(BH_E_OVERFLOW, "walk stack overflow");
+    if (e & kErrTree) return bh_fail(BH_E_DEVICE, "inconsistent tree detected on the device");
+    if (e & kErrNonFinite) return bh_fail(BH_E_DEVICE, "device fault flag: non-finite state or generator failure");
+    return BH_OK;
+}
+
+// ---------------------------------------------------------------- context ---
+
+extern "C" {
+
+const char *bh_last_error(void) { return g_err.c_str(); }
+const char *bh_version(void) { return "bh-mi355x 0.1"; }
+
+bh_status bh_ctx_create(int device, void *hip_stream, bh_ctx **out) {
+    if (!out) return bh_fail(BH_E_INVAL, "out is NULL");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return bh_fail(BH_E_INVAL, "no such device");
+    HIPCHK(hipSetDevice(device));
+    bh_ctx *c = new (std::nothrow) bh_ctx();
+    if (!c) return bh_fail(BH_E_NOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    // small library scratch for the initial-condition reductions and their fault flag
+    hipError_t e = hipMalloc((void **)&c->scratch, sizeof(double) * (6 * 256 + 8));
+    if (e != hipSuccess) {
+        delete c;
+        return bh_fail(BH_E_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipMemset(c->scratch, 0, sizeof(double) * (6 * 256 + 8));
+    if (e != hipSuccess) {
+        (void)hipFree(c->scratch);
+        delete c;
+        return bh_fail(BH_E_DEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return BH_OK;
+}
+
+bh_status bh_ctx_destroy(bh_ctx *ctx) {
+    if (!ctx) return BH_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->scratch);
+    delete ctx;
+    return BH_OK;
+}
+
+bh_status bh_ctx_sync(bh_ctx *ctx) {
+    if (!ctx) return bh_fail(BH_E_INVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BH_OK;
+}
+
+// ------------------------------------------------------------------- tree ---
+
+size_t bh_workspace_bytes(int64_t n, const bh_params *p) {
+    if (n < 1 || !p || bh_check_params(p) != BH_OK) return 0;
+    ForestHost F;
+    return bh_plan_forest(F, 1, &n, p, nullptr);
+}
+
+bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass, const bh_params *p, void *ws,
+                   size_t ws_bytes, bh_tree **out) {
+    if (!ctx || !out || !pos || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = validate_sizes(1, &n, p);
+    if (st != BH_OK) return st;
+    bh_tree *t = new (std::nothrow) bh_tree();
+    if (!t) return bh_fail(BH_E_NOMEM, "host allocation failed");
+    st = bh_forest_init(ctx, t->F, 1, &n, p, ws, ws_bytes);
+    if (st != BH_OK) {
+        delete t;
+        return st;
+    }
+    t->pos = pos;
+    t->mass = mass;
+    hipError_t e = launch_build(t->F.dev, pos, mass, ctx->stream);
+    if (e != hipSuccess) {
+        delete t;
+        return bh_fail(BH_E_DEVICE, std::string("build launch: ") + hipGetErrorString(e));
+    }
+    *out = t;
+    return BH_OK;
+}
+
+bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
+    if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    HIPCHK(launch_upward(t->F.dev, ctx->stream));
+    t->upward_done = true;
+    return BH_OK;
+}
+
+bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
+    if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces");
+    HIPCHK(launch_walk(t->F.dev, t->F.precision, false, acc, pot, nullptr, nullptr, nullptr, ctx->stream));
+    return BH_OK;
+}
+
+bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int64_t *n_mono, int64_t *n_p2p,
+                          uint64_t *hash, bh_stats *totals) {
+    if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
+    HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
+    HIPCHK(launch_walk(t->F.dev, t->F.precision, true, acc, pot, n_mono, n_p2p, hash, ctx->stream));
+    unsigned long long h[4];
+    HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    bh_status st = bh_forest_check_err(t->F);
+    if (st != BH_OK) return st;
+    if (totals) {
+        totals->n_mono = h[0];
+        totals->n_p2p = h[1];
+        totals->n_visits = h[2];
+        totals->n_fallback = h[3];
+    }
+    return BH_OK;
+}
+
+bh_status bh_tree_info(bh_ctx *ctx, bh_tree *t, int64_t *n_nodes, double lo[3], int32_t *k) {
+    if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    SegState s;
+    HIPCHK(hipMemcpyAsync(&s, t->F.dev.st, sizeof(SegState), hipMemcpyDeviceToHost, ctx->stream));
+    bh_status st = bh_forest_check_err(t->F);
+    if (st != BH_OK) return st;
+    if (n_nodes) *n_nodes = s.nn;
+    if (lo) for (int d = 0; d < 3; ++d) lo[d] = s.lo[d];
+    if (k) *k = s.k;
+    return BH_OK;
+}
+
+bh_status bh_tree_export(bh_ctx *ctx, bh_tree *t, uint64_t *keys, uint32_t *perm, int32_t *level, uint32_t *first,
+                         uint32_t *count, int32_t *parent, double *M, double *com) {
+    if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if ((M || com) && !t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before exporting M/com");
+    HIPCHK(launch_export(t->F.dev, 0, keys, perm, level, first, count, parent, M, com, ctx->stream));
+    return BH_OK;
+}
+
+bh_status bh_tree_free(bh_ctx *ctx, bh_tree *t) {
+    (void)ctx;
+    delete t;
+    return BH_OK;
+}
+
+// ------------------------------------------------------------- simulation ---
+
+size_t bh_sim_workspace_bytes(int64_t n, const bh_params *p) { return bh_workspace_bytes(n, p); }
+
+bh_status bh_sim_create(bh_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double *acc,
+                        const bh_params *p, void *ws, size_t ws_bytes, bh_sim **out) {
+    if (!ctx || !out || !pos || !vel || !mass || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = validate_sizes(1, &n, p);
+    if (st != BH_OK) return st;
+    bh_sim *sm = new (std::nothrow) bh_sim();
+    if (!sm) return bh_fail(BH_E_NOMEM, "host allocation failed");
+    st = bh_forest_init(ctx, sm->F, 1, &n, p, ws, ws_bytes);
+    if (st != BH_OK) {
+        delete sm;
+        return st;
+    }
+    sm->pos = pos;
+    sm->vel = vel;
+    sm->mass = mass;
+    sm->acc = acc;
+    *out = sm;
+    return BH_OK;
+}
+
+bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
+    if (!ctx || !sm) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (nsteps < 0 || !std::isfinite(dt)) return bh_fail(BH_E_INVAL, "nsteps must be >= 0 and dt finite");
+    if (sm->F.seg[0].dt != dt) {
+        sm->F.seg[0].dt = dt;
+        bh_status st = bh_forest_upload_seg(sm->F);
+        if (st != BH_OK) return st;
+    }
+    if (!sm->have_acc) {
+        bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, nullptr);
+        if (st != BH_OK) return st;
+        sm->have_acc = true;
+    }
+    for (int32_t k = 0; k < nsteps; ++k) {
+        bh_status st = bh_forest_kdk(sm->F, sm->pos, sm->vel, sm->mass, sm->acc);
+        if (st != BH_OK) return st;
+    }
+    return BH_OK;
+}
+
+bh_status bh_energy(bh_ctx *ctx, bh_sim *sm, double out_KW[2]) {
+    if (!ctx || !sm || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, sm->F.dev.pot);
+    if (st != BH_OK) return st;
+    sm->have_acc = true;
+    HIPCHK(launch_energy(sm->F.dev, sm->vel, sm->mass, sm->F.dev.pot, sm->F.dev.red, ctx->stream));
+    double kw[2];
+    HIPCHK(hipMemcpyAsync(kw, sm->F.dev.red, sizeof(kw), hipMemcpyDeviceToHost, ctx->stream));
+    st = bh_forest_check_err(sm->F);
+    if (st != BH_OK) return st;
+    out_KW[0] = kw[0];
+    out_KW[1] = kw[1];
+    return BH_OK;
+}
+
+bh_status bh_sim_destroy(bh_ctx *ctx, bh_sim *sm) {
+    (void)ctx;
+    delete sm;
+    return BH_OK;
+}
+
+// ----------------------------------------------------------------- forest ---
+
+size_t bh_forest_workspace_bytes(int32_t n_sims, const int64_t *n, const bh_params *per_sim) {
+    if (validate_sizes(n_sims, n, per_sim) != BH_OK) return 0;
+    ForestHost F;
+    return bh_plan_forest(F, n_sims, n, per_sim, nullptr);
+}
+
+bh_status bh_forest_create(bh_ctx *ctx, int32_t n_sims, const int64_t *n, const bh_params *per_sim, double *pos,
+                           double *vel, const double *mass, double *acc, void *ws, size_t ws_bytes, bh_forest **out) {
+    if (!ctx || !out || !pos || !vel || !mass || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = validate_sizes(n_sims, n, per_sim);
+    if (st != BH_OK) return st;
+    bh_forest *fo = new (std::nothrow) bh_forest();
+    if (!fo) return bh_fail(BH_E_NOMEM, "host allocation failed");
+    st = bh_forest_init(ctx, fo->F, n_sims, n, per_sim, ws, ws_bytes);
+    if (st != BH_OK) {
+        delete fo;
+        return st;
+    }
+    fo->pos = pos;
+    fo->vel = vel;
+    fo->mass = mass;
+    fo->acc = acc;
+    *out = fo;
+    return BH_OK;
+}
+
+static bh_status forest_set_dt(bh_forest *fo, const double *dt) {
+    bool changed = false;
+    for (size_t s = 0; s < fo->F.seg.size(); ++s) {
+        if (!std::isfinite(dt[s])) return bh_fail(BH_E_INVAL, "dt must be finite");
+        if (fo->F.seg[s].dt != dt[s]) {
+            fo->F.seg[s].dt = dt[s];
+            changed = true;
+        }
+    }
+    if (changed) {
+        if (fo->graph) {
+            (void)hipGraphExecDestroy(fo->graph);
+            fo->graph = nullptr;
+        }
+        return bh_forest_upload_seg(fo->F);
+    }
+    return BH_OK;
+}
+
+bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const double *dt) {
+    if (!ctx || !fo || !dt) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (nsteps < 0) return bh_fail(BH_E_INVAL, "nsteps must be >= 0");
+    bh_status st = forest_set_dt(fo, dt);
+    if (st != BH_OK) return st;
+    if (!fo->have_acc) {
+        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr);
+        if (st != BH_OK) return st;
+        fo->have_acc = true;
+    }
+    for (int32_t k = 0; k < nsteps; ++k) {
+        st = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc);
+        if (st != BH_OK) return st;
+    }
+    return BH_OK;
+}
+
+bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *fo, double *pot) {
+    if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, pot);
+    if (st == BH_OK) fo->have_acc = true;
+    return st;
+}
+
+bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const double *dt) {
+    if (!ctx || !fo || !dt) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (nsteps < 0) return bh_fail(BH_E_INVAL, "nsteps must be >= 0");
+    bh_status st = forest_set_dt(fo, dt);
+    if (st != BH_OK) return st;
+    if (!fo->have_acc) {
+        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr);
+        if (st != BH_OK) return st;
+        fo->have_acc = true;
+    }
+    hipStream_t s = ctx->stream;
+    if (!fo->graph) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        bh_status cst = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc);
+        hipError_t ee = hipStreamEndCapture(s, &g);
+        if (cst != BH_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cst;
+        }
+        HIPCHK(ee);
+        hipError_t ie = hipGraphInstantiate(&fo->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ie);
+    }
+    for (int32_t k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(fo->graph, s));
+    return BH_OK;
+}
+
+bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *fo) {
+    (void)ctx;
+    if (!fo) return BH_OK;
+    if (fo->graph) (void)hipGraphExecDestroy(fo->graph);
+    delete fo;
+    return BH_OK;
+}
+
+bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *fo, double *out_KW) {
+    if (!ctx || !fo || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
+    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, fo->F.dev.pot);
+    if (st != BH_OK) return st;
+    fo->have_acc = true;
+    HIPCHK(launch_energy(fo->F.dev, fo->vel, fo->mass, fo->F.dev.pot, fo->F.dev.red, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out_KW, fo->F.dev.red, sizeof(double) * 2 * fo->F.seg.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    return bh_forest_check_err(fo->F);
+}
+
+// ---------------------------------------------------- initial conditions ---
+
+bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M, double *pos,
+                         double *vel, double *mass) {
+    if (!ctx || !pos || !vel || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (kind != 0 && kind != 1) return bh_fail(BH_E_INVAL, "kind must be 0 (Plummer) or 1 (cube)");
+    if (n < 1 || n > (int64_t)0x3fffffff) return bh_fail(BH_E_INVAL, "n out of range");
+    if (!(a > 0.0) || !(M > 0.0) || !std::isfinite(a) || !std::isfinite(M))
+        return bh_fail(BH_E_INVAL, "a and M must be positive and finite");
+    HIPCHK(launch_ic(kind, n, seed, a, M, pos, vel, mass, ctx->scratch, ctx->stream));
+    return BH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,750 @@
+// Octree construction and upward pass on gfx950.
+//
+// Build (paper section 1: cubes subdivided recursively until a cube holds at
+// most leaf_cap particles; Fig. 2):
+//   bbox      per-simulation FP64 min/max (order-free integer atomics)
+//   keys      root cube [lo, lo + 2^k)^3, 21-bit quantisation, 63-bit Morton key
+//   sort      stable LSD radix sort of (key, row), 8 passes of 8 bits; a pass is
+//             tile histogram -> one global exclusive scan -> LDS-ranked scatter
+//   permute   FP64 state and FP32 walk copies into key order
+//   lcp       common-prefix level of neighbouring keys
+//   mark/fill canonical compressed octree straight from the sorted keys:
+//             a cube is a node iff it is a leaf of the cube hierarchy or it
+//             holds more than leaf_cap particles spread over >= 2 sub-cubes;
+//             node ids are the depth-first preorder (sort by (first, level))
+// Upward (section 1: centre of mass of each cube): leaves sum their particles
+// in key order, inner nodes their children in octant order, level by level.
+#include "bh_common.h"
+
+namespace bh {
+
+// ============================================================== utilities ===
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// Inclusive scan of one value per thread over a 256-thread block.
+__device__ inline uint32_t block_inclusive_scan_256(uint32_t v, uint32_t *lds_waves /*4*/) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    if (lane == 63) lds_waves[wave] = v;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += lds_waves[w];
+    __syncthreads();
+    return v + add;
+}
+
+// ----------------------------------------------------------------- scans ---
+// Exclusive scan of f(in[i]), i in [0, n), into out[0..n] (out[n] = total).
+// f = identity (kind 0) or popcount (kind 1).  Three kernels: block reduce,
+// one-block scan of the block sums, block scan + offset.
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+template <int KIND>
+__device__ __forceinline__ uint32_t scan_f(uint32_t v) {
+    if (KIND == 1) return (uint32_t)__popc(v);
+    return v;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *in, uint32_t n, uint32_t *bsum) {
+    __shared__ uint32_t w[4];
+    size_t b0 = (size_t)blockIdx.x * kScanBlock;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        size_t i = b0 + (size_t)j * 256 + threadIdx.x;
+        if (i < n) s += scan_f<KIND>(in[i]);
+    }
+    uint32_t inc = block_inclusive_scan_256(s, w);
+    if (threadIdx.x == 255) bsum[blockIdx.x] = inc;
+}
+
+__global__ void __launch_bounds__(256) k_scan_top(uint32_t *bsum, uint32_t nb, uint32_t *total_out) {
+    __shared__ uint32_t w[4];
+    __shared__ uint32_t last;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nb; c0 += 256) {
+        uint32_t i = c0 + threadIdx.x;
+        uint32_t v = i < nb ? bsum[i] : 0;
+        uint32_t inc = block_inclusive_scan_256(v, w);
+        if (i < nb) bsum[i] = carry + inc - v;
+        if (threadIdx.x == 255) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_scan_down(const uint32_t *in, uint32_t n, const uint32_t *bsum,
+                                                   uint32_t *out) {
+    __shared__ uint32_t w[4];
+    size_t b0 = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        size_t i = b0 + j;
+        v[j] = i < n ? scan_f<KIND>(in[i]) : 0;
+        s += v[j];
+    }
+    uint32_t inc = block_inclusive_scan_256(s, w);
+    uint32_t run = bsum[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        size_t i = b0 + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+static hipError_t scan_exclusive(const uint32_t *in, uint32_t n, uint32_t *out, uint32_t *tmp, int kind,
+                                 hipStream_t s) {
+    uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 0) nb = 1;
+    if (kind == 1) hipLaunchKernelGGL(k_scan_reduce<1>, dim3(nb), dim3(256), 0, s, in, n, tmp);
+    else hipLaunchKernelGGL(k_scan_reduce<0>, dim3(nb), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, tmp, nb, out + n);
+    if (kind == 1) hipLaunchKernelGGL(k_scan_down<1>, dim3(nb), dim3(256), 0, s, in, n, tmp, out);
+    else hipLaunchKernelGGL(k_scan_down<0>, dim3(nb), dim3(256), 0, s, in, n, tmp, out);
+    return hipGetLastError();
+}
+
+// ================================================================= segids ===
+
+__global__ void k_segid(ForestDev f) {
+    const TileDesc td = f.tiles[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < td.count; j += blockDim.x) f.segid[td.start + j] = td.seg;
+}
+
+hipError_t launch_segid(const ForestDev &f, hipStream_t s) {
+    if (f.ntiles) hipLaunchKernelGGL(k_segid, dim3(f.ntiles), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+// =================================================================== bbox ===
+
+__global__ void k_seg_reset(ForestDev f) {
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= f.nseg) return;
+    for (int d = 0; d < 3; ++d) {
+        f.st[s].mn[d] = ~0ull;
+        f.st[s].mx[d] = 0ull;
+    }
+    f.st[s].nn = 0;
+}
+
+__global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos) {
+    const TileDesc td = f.tiles[blockIdx.x];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
+        size_t i = (size_t)td.start + j;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = pos[3 * i + d];
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[d] = fmin(mn[d], __shfl_xor(mn[d], o, 64));
+            mx[d] = fmax(mx[d], __shfl_xor(mx[d], o, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0 && td.count > 0) {
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&f.st[td.seg].mn[d], ord_enc(mn[d]));
+            atomicMax(&f.st[td.seg].mx[d], ord_enc(mx[d]));
+        }
+    }
+}
+
+// =================================================================== keys ===
+// q_d = floor(fl(x_d - lo_d) * 2^(21-k)); key = interleave with x the MSB of each digit.
+
+__global__ void __launch_bounds__(kTileThreads) k_keys(ForestDev f, const double *pos) {
+    const TileDesc td = f.tiles[blockIdx.x];
+    __shared__ double lo_s[3], scale_s;
+    if (threadIdx.x == 0) {
+        SegState &st = f.st[td.seg];
+        double lo[3], hi[3], ext = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = ord_dec(st.mn[d]);
+            hi[d] = ord_dec(st.mx[d]);
+            double e = __dsub_rn(hi[d], lo[d]);
+            if (e > ext) ext = e;
+        }
+        int k = 0;
+        if (ext > 0.0) frexp(ext, &k);
+        for (int d = 0; d < 3; ++d) lo_s[d] = lo[d];
+        scale_s = ldexp(1.0, kMaxLevel - k);
+        if (blockIdx.x == f.seg[td.seg].tile_base) {
+            for (int d = 0; d < 3; ++d) {
+                st.lo[d] = lo[d];
+                st.cref[d] = 0.5 * lo[d] + 0.5 * hi[d];
+            }
+            st.k = k;
+            st.L = ldexp(1.0, k);
+        }
+    }
+    __syncthreads();
+    const double scale = scale_s;
+    for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
+        size_t i = (size_t)td.start + j;
+        uint64_t q[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double c = floor(__dmul_rn(__dsub_rn(pos[3 * i + d], lo_s[d]), scale));
+            c = fmin(fmax(c, 0.0), 2097151.0);
+            q[d] = (uint64_t)c;
+        }
+        f.keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+        f.idx[i] = (uint32_t)i;
+    }
+}
+
+// =================================================================== sort ===
+// Stable within a tile: items are ranked in element order with wave-level
+// digit matching (8 ballots) and per-wave LDS counters.
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t dig, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        uint64_t m = __ballot((dig >> b) & 1u);
+        peers &= ((dig >> b) & 1u) ? m : ~m;
+    }
+    return peers;
+}
+
+__device__ __forceinline__ uint32_t cnt_index(const SegDesc &sd, uint32_t tile, uint32_t digit) {
+    return 256u * sd.tile_base + digit * sd.ntiles + (tile - sd.tile_base);
+}
+
+__global__ void __launch_bounds__(kTileThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
+    __shared__ uint32_t hist[4][256];
+    const TileDesc td = f.tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = lane; d < 256; d += 64) hist[wave][d] = 0;
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll 4
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+        bool valid = e < td.count;
+        uint32_t dig = valid ? (uint32_t)(keys[(size_t)td.start + e] >> shift) & 255u : 0u;
+        uint64_t peers = match_digit(dig, __ballot(valid));
+        if (valid && (peers & lt) == 0) hist[wave][dig] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    const SegDesc sd = f.seg[td.seg];
+    uint32_t d = threadIdx.x;
+    f.cnt[cnt_index(sd, blockIdx.x, d)] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+}
+
+__global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
+                                                               uint64_t *kout, uint32_t *iout, int shift) {
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sidx[kTile];
+    __shared__ uint32_t whist[4][256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t wtot[4];
+    const TileDesc td = f.tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int d = lane; d < 256; d += 64) whist[wave][d] = 0;
+    __syncthreads();
+
+    uint64_t key[kItems];
+    uint32_t idv[kItems];
+    uint32_t rank[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+        bool valid = e < td.count;
+        key[j] = valid ? kin[(size_t)td.start + e] : 0ull;
+        idv[j] = valid ? iin[(size_t)td.start + e] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+        bool valid = e < td.count;
+        uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
+        uint64_t peers = match_digit(dig, __ballot(valid));
+        uint32_t before = valid ? whist[wave][dig] : 0u;
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) whist[wave][dig] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of the waves, tile-local start, global base
+    {
+        uint32_t d = threadIdx.x;
+        uint32_t c0 = whist[0][d], c1 = whist[1][d], c2 = whist[2][d], c3 = whist[3][d];
+        uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t inc = block_inclusive_scan_256(tot, wtot);
+        lstart[d] = inc - tot;
+        whist[0][d] = 0;
+        whist[1][d] = c0;
+        whist[2][d] = c0 + c1;
+        whist[3][d] = c0 + c1 + c2;
+        const SegDesc sd = f.seg[td.seg];
+        gbase[d] = f.cnt[cnt_index(sd, blockIdx.x, d)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+        if (e < td.count) {
+            uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
+            uint32_t p = lstart[dig] + whist[wave][dig] + rank[j];
+            skey[p] = key[j];
+            sidx[p] = idv[j];
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < td.count; q += kTileThreads) {
+        uint64_t k = skey[q];
+        uint32_t dig = (uint32_t)(k >> shift) & 255u;
+        uint32_t o = gbase[dig] + (q - lstart[dig]);
+        kout[o] = k;
+        iout[o] = sidx[q];
+    }
+}
+
+// ================================================================ permute ===
+
+__global__ void k_permute(ForestDev f, const double *pos, const double *mass) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= f.ntot) return;
+    uint32_t i = f.idx[r];
+    double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
+    double m = mass[i];
+    f.spos[3 * (size_t)r] = x;
+    f.spos[3 * (size_t)r + 1] = y;
+    f.spos[3 * (size_t)r + 2] = z;
+    f.smass[r] = m;
+}
+
+// ==================================================================== lcp ===
+// lcp[p], p in [0, ntot]: octant digits shared by keys p-1 and p (21 if equal),
+// -1 at the first row of a simulation and at ntot.  Also clears mask.
+
+__global__ void k_lcp(ForestDev f) {
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > f.ntot) return;
+    int8_t v = -1;
+    if (p < f.ntot) {
+        f.mask[p] = 0;
+        uint32_t s = f.segid[p];
+        if (p != f.seg[s].start) {
+            uint64_t x = f.keys[p - 1] ^ f.keys[p];
+            v = x == 0 ? (int8_t)kMaxLevel : (int8_t)((__clzll((long long)x) - 1) / 3);
+        }
+    }
+    f.lcp[p] = v;
+}
+
+// ============================================================ node marking ===
+
+struct Seg { uint32_t lo, hi, cap; };
+
+__device__ __forceinline__ Seg seg_of(const ForestDev &f, uint32_t r) {
+    const SegDesc &sd = f.seg[f.segid[r]];
+    Seg s;
+    s.lo = sd.start;
+    s.hi = sd.start + sd.n;
+    s.cap = (uint32_t)sd.leaf_cap;
+    return s;
+}
+
+// Level of the leaf holding row r: one below the deepest cube (level <= 20) with more
+// than cap particles.  Returns 0 when the whole simulation fits one leaf.
+__device__ inline int leaf_level(const ForestDev &f, uint32_t r, const Seg &sg) {
+    if (sg.hi - sg.lo <= sg.cap) return 0;
+    int h;
+    if (sg.cap == 1) {
+        int a = f.lcp[r], b = f.lcp[r + 1];
+        h = a > b ? a : b;
+        if (h > kMaxLevel - 1) h = kMaxLevel - 1;
+    } else {
+        int lo = 0, hi = kMaxLevel;          // cnt(lo) > cap, level hi excluded
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            uint32_t a = cell_left(f.keys, r, mid, sg.lo);
+            uint32_t b = cell_right(f.keys, r, mid, sg.hi);
+            if (b - a > sg.cap) lo = mid; else hi = mid;
+        }
+        h = lo;
+    }
+    return h + 1;
+}
+
+__device__ __forceinline__ uint32_t node_id(const ForestDev &f, uint32_t first, int level) {
+    return f.base[first] + (uint32_t)__popc(f.mask[first] & ((1u << level) - 1u));
+}
+
+// Mark pass: every node sets bit `level` of mask[first].
+__global__ void __launch_bounds__(256) k_mark(ForestDev f) {
+    __shared__ uint32_t lcount[32];
+    if (threadIdx.x < 32) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < f.ntot) {
+        const Seg sg = seg_of(f, r);
+        // leaf holding r, marked by its first row
+        int lam = leaf_level(f, r, sg);
+        uint32_t a = lam == 0 ? sg.lo : cell_left(f.keys, r, lam, sg.lo);
+        if (a == r) atomicOr(&f.mask[a], 1u << lam);
+        // inner node owned by boundary r (the first split of its cube)
+        int l = f.lcp[r];
+        if (l >= 0 && l < kMaxLevel) {
+            uint32_t q = cell_left(f.keys, r - 1, l + 1, sg.lo);
+            if (q == sg.lo || f.lcp[q] < l) {
+                uint32_t R = cell_right(f.keys, r, l, sg.hi);
+                if (R - q > sg.cap) {
+                    atomicOr(&f.mask[q], 1u << l);
+                    atomicAdd(&lcount[l], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLevel && lcount[threadIdx.x]) atomicAdd(&f.level_cnt[threadIdx.x], lcount[threadIdx.x]);
+}
+
+__global__ void k_level_offsets(ForestDev f) {
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int l = 0; l < 32; ++l) {
+            f.level_off[l] = run;
+            run += f.level_cnt[l];
+            f.level_cur[l] = 0;
+        }
+    }
+}
+
+// Fill pass: node records at their preorder ids, child links, level buckets.
+__global__ void __launch_bounds__(256) k_fill(ForestDev f) {
+    __shared__ uint32_t lcount[32], lbase[32];
+    if (threadIdx.x < 32) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    int my_level = -1;
+    uint32_t my_node = 0, my_off = 0;
+    if (r < f.ntot) {
+        const uint32_t s = f.segid[r];
+        const Seg sg = seg_of(f, r);
+        int lam = leaf_level(f, r, sg);
+        uint32_t a = lam == 0 ? sg.lo : cell_left(f.keys, r, lam, sg.lo);
+        if (a == r) {
+            uint32_t b = lam == 0 ? sg.hi : cell_right(f.keys, r, lam, sg.hi);
+            uint32_t g = node_id(f, a, lam);
+            f.nlevel[g] = (uint8_t)lam;
+            f.nfirst[g] = a;
+            f.ncount[g] = b - a;
+            f.nchild[g] = 0;
+            if (a == sg.lo && (f.mask[a] & ((1u << lam) - 1u)) == 0) {
+                f.nparent[g] = kNone;
+                f.ncrank[g] = s;
+                f.st[s].nbase = g;
+            }
+        }
+        int l = f.lcp[r];
+        if (l >= 0 && l < kMaxLevel) {
+            uint32_t q = cell_left(f.keys, r - 1, l + 1, sg.lo);
+            if (q == sg.lo || f.lcp[q] < l) {
+                uint32_t R = cell_right(f.keys, r, l, sg.hi);
+                if (R - q > sg.cap) {
+                    uint32_t g = node_id(f, q, l);
+                    f.nlevel[g] = (uint8_t)l;
+                    f.nfirst[g] = q;
+                    f.ncount[g] = R - q;
+                    if (q == sg.lo && (f.mask[q] & ((1u << l) - 1u)) == 0) {
+                        f.nparent[g] = kNone;
+                        f.ncrank[g] = s;
+                        f.st[s].nbase = g;
+                    }
+                    // children: the level-(l+1) cubes partitioning [q, R)
+                    uint32_t c0 = q, k = 0;
+                    while (c0 < R && k < 8) {
+                        uint32_t c1 = cell_right(f.keys, c0, l + 1, R);
+                        uint32_t c = f.base[c0] + (uint32_t)__popc(f.mask[c0] & ((2u << l) - 1u));
+                        f.nparent[c] = g;
+                        f.ncrank[c] = k;
+                        ++k;
+                        c0 = c1;
+                    }
+                    f.nchild[g] = k;
+                    my_level = l;
+                    my_node = g;
+                    my_off = atomicAdd(&lcount[l], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLevel) lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&f.level_cur[threadIdx.x], lcount[threadIdx.x]) : 0;
+    __syncthreads();
+    if (my_level >= 0) {
+        uint32_t at = f.level_off[my_level] + lbase[my_level] + my_off;
+        if (at <= f.ntot) f.level_list[at] = my_node;
+        else atomicOr(f.err, kErrTree);
+    }
+}
+
+// Walk slots: roots take slots [0, nseg); the children of node g take
+// [nseg + cs[g], nseg + cs[g] + nchild[g]) in octant order.
+__global__ void k_slots(ForestDev f) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t mtot = f.base[f.ntot];
+    if (g >= mtot) return;
+    uint32_t p = f.nparent[g];
+    uint32_t rk = f.ncrank[g];
+    uint32_t sl;
+    if (p == kNone) {
+        sl = rk;
+        if (rk >= f.nseg) { atomicOr(f.err, kErrTree); return; }
+    } else {
+        if (p >= mtot || rk >= 8) { atomicOr(f.err, kErrTree); return; }
+        sl = f.nseg + f.cs[p] + rk;
+    }
+    if (sl >= mtot) { atomicOr(f.err, kErrTree); return; }
+    f.slot_of[g] = sl;
+    f.node_at_slot[sl] = g;
+}
+
+__global__ void k_seg_nodes(ForestDev f) {
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= f.nseg) return;
+    const SegDesc &sd = f.seg[s];
+    f.st[s].nn = f.base[sd.start + sd.n] - f.base[sd.start];
+}
+
+hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass, hipStream_t s) {
+    const unsigned segb = (f.nseg + 255) / 256;
+    hipLaunchKernelGGL(k_seg_reset, dim3(segb), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
+    hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
+    // 8 stable passes of 8 bits: the result returns to (keys, idx)
+    const uint32_t ncnt = 256u * f.ntiles;
+    uint64_t *kin = f.keys, *kout = f.keys_alt;
+    uint32_t *iin = f.idx, *iout = f.idx_alt;
+    for (int pass = 0; pass < 8; ++pass) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, shift);
+        hipError_t e = scan_exclusive(f.cnt, ncnt, f.cnt, f.scan_tmp, 0, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, iin, kout, iout, shift);
+        uint64_t *tk = kin; kin = kout; kout = tk;
+        uint32_t *ti = iin; iin = iout; iout = ti;
+    }
+    const unsigned nb = (f.ntot + 255) / 256;
+    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, s, f, pos, mass);
+    hipLaunchKernelGGL(k_lcp, dim3((f.ntot + 1 + 255) / 256), dim3(256), 0, s, f);
+    hipError_t e = launch_fill_u32(f.level_cnt, 0, 32, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mark, dim3(nb), dim3(256), 0, s, f);
+    e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, f);
+    e = launch_fill_u32(f.nchild, 0, f.mcap, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(f.nparent, kNone, f.mcap, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(f.ncrank, kNone, f.mcap, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(f.node_at_slot, kNone, f.mcap, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, f);
+    e = scan_exclusive(f.nchild, f.mcap, f.cs, f.scan_tmp, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_slots, dim3((f.mcap + 255) / 256), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_seg_nodes, dim3(segb), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+// ================================================================= upward ===
+
+__global__ void k_up_leaf(ForestDev f) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t mtot = f.base[f.ntot];
+    if (g >= mtot || f.nchild[g] != 0) return;
+    uint32_t a = f.nfirst[g], b = a + f.ncount[g];
+    if (a >= f.ntot || b > f.ntot || b <= a) { atomicOr(f.err, kErrTree); return; }
+    double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    for (uint32_t r = a; r < b; ++r) {
+        double m = f.smass[r];
+        M = __dadd_rn(M, m);
+        Sx = __dadd_rn(Sx, __dmul_rn(m, f.spos[3 * (size_t)r]));
+        Sy = __dadd_rn(Sy, __dmul_rn(m, f.spos[3 * (size_t)r + 1]));
+        Sz = __dadd_rn(Sz, __dmul_rn(m, f.spos[3 * (size_t)r + 2]));
+    }
+    f.nM[g] = M;
+    f.nS[3 * (size_t)g] = Sx;
+    f.nS[3 * (size_t)g + 1] = Sy;
+    f.nS[3 * (size_t)g + 2] = Sz;
+}
+
+__global__ void k_up_level(ForestDev f, int level) {
+    const uint32_t n = f.level_cnt[level], off = f.level_off[level];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t g = f.level_list[off + i];
+        const uint32_t mtot = f.base[f.ntot];
+        if (g >= mtot) { atomicOr(f.err, kErrTree); continue; }
+        uint32_t c0 = f.nseg + f.cs[g], nc = f.nchild[g];
+        if (nc < 2 || nc > 8 || c0 + nc > mtot) { atomicOr(f.err, kErrTree); continue; }
+        bool bad = false;
+        for (uint32_t k = 0; k < nc; ++k) bad |= f.node_at_slot[c0 + k] >= mtot;
+        if (bad) { atomicOr(f.err, kErrTree); continue; }
+        double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+        for (uint32_t k = 0; k < nc; ++k) {
+            uint32_t c = f.node_at_slot[c0 + k];
+            M = __dadd_rn(M, f.nM[c]);
+            Sx = __dadd_rn(Sx, f.nS[3 * (size_t)c]);
+            Sy = __dadd_rn(Sy, f.nS[3 * (size_t)c + 1]);
+            Sz = __dadd_rn(Sz, f.nS[3 * (size_t)c + 2]);
+        }
+        f.nM[g] = M;
+        f.nS[3 * (size_t)g] = Sx;
+        f.nS[3 * (size_t)g + 1] = Sy;
+        f.nS[3 * (size_t)g + 2] = Sz;
+    }
+}
+
+// com = S / M, then the walk record of the node at its slot.
+__global__ void k_records(ForestDev f) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t mtot = f.base[f.ntot];
+    if (g >= mtot) return;
+    double M = f.nM[g];
+    double c[3];
+    for (int d = 0; d < 3; ++d) {
+        c[d] = f.nS[3 * (size_t)g + d] / M;
+        f.nS[3 * (size_t)g + d] = c[d];
+    }
+    const uint32_t sid = f.segid[f.nfirst[g]];
+    const SegDesc &sd = f.seg[sid];
+    const SegState &st = f.st[sid];
+    const int level = f.nlevel[g];
+    const uint32_t nc = f.nchild[g];
+    const uint32_t link = nc ? f.nseg + f.cs[g] : f.nfirst[g];
+    const uint32_t cnt = nc ? nc : (f.ncount[g] | kLeafBit);
+    const uint32_t sl = f.slot_of[g];
+    if (sl >= mtot || (nc && (nc < 2 || nc > 8 || link + nc > mtot)) ||
+        (!nc && (link >= f.ntot || f.ncount[g] == 0 || link + f.ncount[g] > f.ntot))) {
+        atomicOr(f.err, kErrTree);
+        return;
+    }
+    const double s = ldexp(st.L, -level);
+    if (sd.precision == 1) {
+        WRec32 w;
+        w.cx = c[0];
+        w.cy = c[1];
+        w.cz = c[2];
+        w.m = (float)M;
+        // FP32 opening test band (see the walk): exact side^2 when in FP32 range, else always FP64
+        const int e2 = 2 * (st.k - level);
+        const double u = 5.9604644775390625e-8;   // 2^-24
+        if (e2 > -120 && e2 < 120) {
+            w.S = ldexpf(1.0f, e2);
+            w.band0 = (float)(16.0 * u * ldexp(1.0, e2));
+            w.band1 = (float)(8.0 * u * s * sd.theta * (1.0 + 1e-6));
+        } else {
+            w.S = 0.0f;
+            w.band0 = INFINITY;
+            w.band1 = 0.0f;
+        }
+        w.link = link;
+        w.cnt = cnt;
+        w.gid = g;
+        w.level = (uint32_t)level;
+        w.pad[0] = w.pad[1] = 0;
+        f.w32[sl] = w;
+    } else {
+        WRec64 w;
+        w.x = c[0];
+        w.y = c[1];
+        w.z = c[2];
+        w.m = M;
+        w.S = __dmul_rn(s, s);
+        w.link = link;
+        w.cnt = cnt;
+        w.gid = g;
+        w.level = (uint32_t)level;
+        w.pad = 0.0;
+        f.w64[sl] = w;
+    }
+}
+
+hipError_t launch_upward(const ForestDev &f, hipStream_t s) {
+    const unsigned mb = (f.mcap + 255) / 256;
+    hipLaunchKernelGGL(k_up_leaf, dim3(mb), dim3(256), 0, s, f);
+    unsigned lb = (f.ntot / 2 + 255) / 256;
+    if (lb < 1) lb = 1;
+    if (lb > 2048) lb = 2048;
+    for (int l = kMaxLevel - 1; l >= 0; --l)
+        hipLaunchKernelGGL(k_up_level, dim3(lb), dim3(256), 0, s, f, l);
+    hipLaunchKernelGGL(k_records, dim3(mb), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+// ================================================================= export ===
+// Canonical arrays of simulation `seg` in its own numbering (ranks and node ids
+// relative to the simulation).
+
+__global__ void k_export_particles(ForestDev f, uint32_t seg, uint64_t *keys, uint32_t *perm) {
+    const SegDesc &sd = f.seg[seg];
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= sd.n) return;
+    if (keys) keys[r] = f.keys[sd.start + r];
+    if (perm) perm[r] = f.idx[sd.start + r] - sd.start;
+}
+
+__global__ void k_export_nodes(ForestDev f, uint32_t seg, int32_t *level, uint32_t *first, uint32_t *count,
+                               int32_t *parent, double *M, double *com) {
+    const SegDesc &sd = f.seg[seg];
+    const SegState &st = f.st[seg];
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= st.nn) return;
+    uint32_t g = st.nbase + j;
+    if (level) level[j] = f.nlevel[g];
+    if (first) first[j] = f.nfirst[g] - sd.start;
+    if (count) count[j] = f.ncount[g];
+    if (parent) parent[j] = f.nparent[g] == kNone ? -1 : (int32_t)(f.nparent[g] - st.nbase);
+    if (M) M[j] = f.nM[g];
+    if (com)
+        for (int d = 0; d < 3; ++d) com[3 * (size_t)j + d] = f.nS[3 * (size_t)g + d];
+}
+
+hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,
+                         uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_export_particles, dim3((f.ntot + 255) / 256), dim3(256), 0, s, f, seg, keys, perm);
+    hipLaunchKernelGGL(k_export_nodes, dim3((f.mcap + 255) / 256), dim3(256), 0, s, f, seg, level, first, count,
+                       parent, M, com);
+    return hipGetLastError();
+}
+
+}  // namespace bh

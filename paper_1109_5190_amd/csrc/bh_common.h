@@ -1,0 +1,200 @@
+// Shared definitions of the MI355X Barnes-Hut library: device data layouts,
+// small device helpers and the host-side launcher prototypes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bh {
+
+constexpr int kMaxLevel = 21;          // 63-bit Morton keys: 21 octant digits
+constexpr int kTile = 4096;            // particles per sort / bbox tile
+constexpr int kTileThreads = 256;
+constexpr int kItems = kTile / kTileThreads;   // 16 keys per thread in the sort
+constexpr int kGroup = 64;             // walk targets per wavefront
+constexpr int kWalkThreads = 256;      // 4 wavefronts per block
+constexpr int kStackMax = 160;         // >= 1 + 7 * 21 entries of (child block, lane mask)
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kNone = 0xffffffffu;
+
+// error word bits
+constexpr uint32_t kErrStack = 1u;
+constexpr uint32_t kErrNonFinite = 2u;
+constexpr uint32_t kErrTree = 4u;      // inconsistent tree: the walk is skipped
+
+// Per simulation, fixed at forest creation (host written).
+struct SegDesc {
+    uint32_t start, n;          // particle rows [start, start + n) of the concatenated arrays
+    uint32_t tile_base, ntiles; // sort tiles of this simulation
+    uint32_t group_base, ngroups;
+    int32_t leaf_cap, precision;
+    double theta, eps, G;
+    double dt;
+};
+
+// Per simulation, written on the device by every build.
+struct SegState {
+    unsigned long long mn[3], mx[3];   // order-preserving integer images of the bbox
+    double lo[3];                      // root cube minimum corner
+    double cref[3];                    // FP32 coordinate origin (bbox centre)
+    double L;                          // root cube side 2^k
+    int32_t k;
+    uint32_t nbase;                    // global id of the root node
+    uint32_t nn;                       // nodes of this simulation
+    uint32_t pad[3];
+};
+
+struct TileDesc { uint32_t start, count, seg, pad; };
+struct GroupDesc { uint32_t start, count, seg, pad; };
+
+// Walk record of a node, FP32 mode (indexed by walk slot: children of a node are contiguous).
+// The centre of mass stays FP64 so that every wavefront can re-express it relative to its
+// own reference point before rounding to FP32.
+struct WRec32 {
+    double cx, cy, cz;         // centre of mass (FP64)
+    float m;                   // mass (FP32)
+    float S;                   // side^2 (exact power of two; 0 if out of FP32 range)
+    float band0;               // rounding band of the FP32 opening test: 16 u S (inf: always FP64)
+    float band1;               // ... plus rho * (band1 + 4 u^2 theta^2 rho), band1 = 8 u s theta
+    uint32_t link;             // internal: first child slot; leaf: first particle rank
+    uint32_t cnt;              // internal: children; leaf: particles | kLeafBit
+    uint32_t gid;              // global node id (depth-first preorder)
+    uint32_t level;
+    uint32_t pad[2];
+};
+
+// Walk record of a node, FP64 mode.
+struct WRec64 {
+    double x, y, z, m;
+    double S;
+    uint32_t link, cnt, gid, level;
+    double pad;
+};
+
+// Device-side views of one forest's buffers (all sub-allocated from the caller's workspace).
+struct ForestDev {
+    uint32_t nseg, ntot, ntiles, ngroups, mcap;
+    SegDesc *seg;
+    SegState *st;
+    TileDesc *tiles;
+    GroupDesc *groups;
+    uint32_t *segid;            // per particle row
+    uint64_t *keys, *keys_alt;  // sort ping-pong
+    uint32_t *idx, *idx_alt;    // idx ends as perm: sorted rank -> original row
+    uint32_t *cnt;              // sort digit counts, 256 per tile (+1 total)
+    uint32_t *scan_tmp;         // block sums of the scans
+    double *spos, *smass;       // sorted state (FP64)
+    int8_t *lcp;                // common-prefix level of neighbouring keys, -1 at segment edges
+    uint32_t *mask;             // per row: bit l set if a node of level l starts at this row
+    uint32_t *base;             // exclusive scan of popcount(mask): global node id base
+    uint8_t *nlevel;            // per node
+    uint32_t *nchild;           // per node (scan input: number of children)
+    uint32_t *nfirst, *ncount, *nparent, *ncrank;
+    uint32_t *cs;               // exclusive scan of nchild
+    uint32_t *slot_of, *node_at_slot;
+    uint32_t *level_cnt, *level_off, *level_cur, *level_list;  // internal nodes bucketed by level
+    double *nM, *nS;            // node mass, centre of mass (FP64; S then com in place)
+    WRec32 *w32;
+    WRec64 *w64;
+    uint32_t *err;              // device error word
+    unsigned long long *stats;  // 4 totals (n_mono, n_p2p, n_visits, n_fallback)
+    double *red;                // reduction scratch (energy)
+    double *pot;                // potential scratch (ntot)
+};
+
+// ---------------------------------------------------------------- helpers ---
+
+__device__ __forceinline__ unsigned long long ord_enc(double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_dec(unsigned long long e) {
+    unsigned long long b = (e & 0x8000000000000000ull) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double((long long)b);
+}
+
+// Morton spread: bit b of v moves to bit 3b (v < 2^21).
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// SplitMix64 finalizer of x + golden gamma (interaction-set checksum).
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// First row q in [lo, r] whose key shares r's level-`level` cube (keys sorted on [lo, hi)).
+__device__ inline uint32_t cell_left(const uint64_t *K, uint32_t r, int level, uint32_t lo) {
+    if (level <= 0) return lo;
+    const int sh = 3 * (kMaxLevel - level);
+    const uint64_t P = K[r] >> sh;
+    uint32_t good = r, bad, step = 1;
+    for (;;) {
+        if (good - lo < step) {
+            if ((K[lo] >> sh) == P) return lo;
+            bad = lo;
+            break;
+        }
+        uint32_t q = good - step;
+        if ((K[q] >> sh) == P) { good = q; step <<= 1; }
+        else { bad = q; break; }
+    }
+    while (good - bad > 1) {
+        uint32_t mid = bad + (good - bad) / 2;
+        if ((K[mid] >> sh) == P) good = mid; else bad = mid;
+    }
+    return good;
+}
+
+// One past the last row q in [r, hi) whose key shares r's level-`level` cube.
+__device__ inline uint32_t cell_right(const uint64_t *K, uint32_t r, int level, uint32_t hi) {
+    if (level <= 0) return hi;
+    const int sh = 3 * (kMaxLevel - level);
+    const uint64_t P = K[r] >> sh;
+    uint32_t good = r, bad, step = 1;
+    for (;;) {
+        if (hi - 1 - good < step) {
+            if ((K[hi - 1] >> sh) == P) return hi;
+            bad = hi - 1;
+            break;
+        }
+        uint32_t q = good + step;
+        if ((K[q] >> sh) == P) { good = q; step <<= 1; }
+        else { bad = q; break; }
+    }
+    while (bad - good > 1) {
+        uint32_t mid = good + (bad - good) / 2;
+        if ((K[mid] >> sh) == P) good = mid; else bad = mid;
+    }
+    return good + 1;
+}
+
+// ------------------------------------------------------ launcher prototypes ---
+// All launchers enqueue on `s` and return hipGetLastError().
+
+hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass,
+                        hipStream_t s);                          // bbox .. tree topology
+hipError_t launch_upward(const ForestDev &f, hipStream_t s);     // masses, centres, walk records
+hipError_t launch_walk(const ForestDev &f, int precision, bool stats, double *acc, double *pot,
+                       int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, hipStream_t s);
+hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, double half, hipStream_t s);
+hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, hipStream_t s);
+hipError_t launch_energy(const ForestDev &f, const double *vel, const double *mass, const double *pot,
+                         double *out2, hipStream_t s);
+hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,
+                         uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com,
+                         hipStream_t s);
+hipError_t launch_ic(int kind, int64_t n, uint64_t seed, double a, double M, double *pos, double *vel,
+                     double *mass, double *scratch, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_segid(const ForestDev &f, hipStream_t s);
+
+}  // namespace bh

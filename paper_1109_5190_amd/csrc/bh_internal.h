@@ -1,0 +1,56 @@
+// Host-side objects behind the opaque C handles.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "bh.h"
+#include "bh_common.h"
+
+struct bh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double *scratch = nullptr;   // initial-condition reductions (6 x 256 doubles) + fault flag
+};
+
+struct ForestHost {
+    bh::ForestDev dev{};
+    std::vector<bh::SegDesc> seg;
+    std::vector<bh::TileDesc> tiles;
+    std::vector<bh::GroupDesc> groups;
+    int precision = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bh_ctx *ctx = nullptr;
+};
+
+struct bh_tree {
+    ForestHost F;
+    const double *pos = nullptr;
+    const double *mass = nullptr;
+    bool upward_done = false;
+};
+
+struct bh_sim {
+    ForestHost F;
+    double *pos = nullptr, *vel = nullptr, *acc = nullptr;
+    const double *mass = nullptr;
+    bool have_acc = false;
+};
+
+struct bh_forest {
+    ForestHost F;
+    double *pos = nullptr, *vel = nullptr, *acc = nullptr;
+    const double *mass = nullptr;
+    bool have_acc = false;
+    hipGraphExec_t graph = nullptr;
+};
+
+bh_status bh_fail(bh_status st, const std::string &msg);
+bh_status bh_check_params(const bh_params *p);
+size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws);
+bh_status bh_forest_init(bh_ctx *ctx, ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, void *ws,
+                         size_t ws_bytes);
+bh_status bh_forest_upload_seg(ForestHost &F);
+bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot);
+bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc);
+bh_status bh_forest_check_err(ForestHost &F);

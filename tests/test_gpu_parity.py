@@ -1,0 +1,138 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same
+seeded inputs.  Keys, order, topology, masses and centres of mass bit-exact;
+forces within the FP64 (1e-10 RMS) and FP32 (2e-6 RMS, 1e-4 max) gates with
+per-body interaction counts and set checksums equal."""
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.gpu_helpers import dev, rel_max, rel_rms, u64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bh = pytest.importorskip("paper_1109_5190_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = bh.Context(0)
+    yield c
+    c.sync()
+
+
+def system(kind, n, seed):
+    if kind == "plummer":
+        return icgen.plummer(n, seed)
+    if kind == "uniform":
+        return icgen.uniform_cube(n, seed)
+    if kind == "duplicates":
+        s = icgen.plummer(n, seed)
+        pos = np.round(s.pos * 4.0) / 4.0
+        pos[: n // 4] = pos[0]
+        return icgen.System(pos, s.vel, s.mass)
+    if kind == "coincident":
+        return icgen.System(np.tile([[0.25, -1.5, 3.0]], (n, 1)), np.zeros((n, 3)), np.full(n, 1.0 / n))
+    if kind == "two_spheres":
+        h = n // 2
+        return icgen.two_plummer(h, seed, seed + 1)
+    raise ValueError(kind)
+
+
+TREE_CASES = [
+    ("plummer", 4096, 1, 1),      # the small workload: one tile
+    ("plummer", 4096, 1, 16),
+    ("uniform", 10001, 5, 1),     # three tiles with a ragged tail
+    ("duplicates", 5000, 7, 1),
+    ("duplicates", 5000, 7, 8),
+    ("two_spheres", 9000, 3, 4),
+    ("plummer", 1, 2, 1),
+    ("plummer", 2, 2, 1),
+    ("coincident", 3, 0, 1),
+    ("coincident", 700, 0, 16),
+    ("plummer", 64, 9, 64),       # whole system in one leaf
+    ("plummer", 65, 9, 64),
+]
+
+
+@pytest.mark.parametrize("kind,n,seed,leaf_cap", TREE_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tree_bit_exact(ctx, kind, n, seed, leaf_cap, prec):
+    print(f"[tree] {kind} n={n} seed={seed} leaf_cap={leaf_cap} {prec}", flush=True)
+    s = system(kind, n, seed)
+    T = oracle.Tree(s.pos, s.mass, leaf_cap)
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.5, 0.01, leaf_cap=leaf_cap, precision=prec)).upward()
+    ex = t.export()
+    ctx.sync()
+    assert ex["n_nodes"] == T.nn
+    assert ex["k"] == T.k and np.array_equal(np.array(ex["lo"]), T.lo)
+    assert np.array_equal(u64(ex["keys"]), T.keys)
+    assert np.array_equal(ex["perm"].cpu().numpy().astype(np.uint32), T.perm)
+    assert np.array_equal(ex["level"].cpu().numpy(), T.level)
+    assert np.array_equal(ex["first"].cpu().numpy().astype(np.uint32), T.first)
+    assert np.array_equal(ex["count"].cpu().numpy().astype(np.uint32), T.count)
+    assert np.array_equal(ex["parent"].cpu().numpy(), T.parent)
+    assert np.array_equal(ex["M"].cpu().numpy(), T.M)           # bit-exact FP64
+    assert np.array_equal(ex["com"].cpu().numpy(), T.com)
+
+
+WALK_CASES = [
+    ("plummer", 4096, 1, 0.5, 0.01, 1),
+    ("plummer", 4096, 1, 0.5, 0.01, 16),
+    ("plummer", 4096, 1, 0.3, 0.01, 1),
+    ("plummer", 4096, 1, 0.7, 0.01, 1),
+    ("plummer", 4096, 1, 1.0, 0.01, 1),
+    ("uniform", 20001, 5, 0.5, 0.005, 1),
+    ("two_spheres", 20000, 3, 0.5, 0.005, 4),
+    ("duplicates", 5000, 7, 0.6, 0.01, 2),
+]
+
+
+@pytest.mark.parametrize("kind,n,seed,theta,eps,leaf_cap", WALK_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_walk_parity(ctx, kind, n, seed, theta, eps, leaf_cap, prec):
+    print(f"[walk] {kind} n={n} theta={theta} leaf_cap={leaf_cap} {prec}", flush=True)
+    s = system(kind, n, seed)
+    ref = oracle.forces(s.pos, s.mass, theta=theta, eps=eps, leaf_cap=leaf_cap)
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(theta, eps, leaf_cap=leaf_cap, precision=prec)).upward()
+    r = t.forces_stats(pot=True)
+    ctx.sync()
+    assert np.array_equal(r["n_mono"].cpu().numpy(), ref["n_mono"])
+    assert np.array_equal(r["n_p2p"].cpu().numpy(), ref["n_p2p"])
+    assert np.array_equal(u64(r["hash"]), ref["hash"])
+    acc = r["acc"].cpu().numpy()
+    pot = r["pot"].cpu().numpy()
+    if prec == "fp64":
+        assert rel_rms(acc, ref["acc"]) <= 1e-10
+        assert rel_rms(pot[:, None], ref["pot"][:, None]) <= 1e-10
+    else:
+        assert rel_rms(acc, ref["acc"]) <= 2e-6
+        assert rel_max(acc, ref["acc"]) <= 1e-4
+        assert rel_rms(pot[:, None], ref["pot"][:, None]) <= 2e-6
+    tot = r["totals"]
+    assert tot["n_mono"] == ref["n_mono"].sum() and tot["n_p2p"] == ref["n_p2p"].sum()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_theta_zero_is_direct_sum(ctx, prec):
+    s = icgen.plummer(3000, 4)
+    d = oracle.direct(s.pos, s.mass, eps=0.01)
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.0, 0.01, precision=prec)).upward()
+    r = t.forces_stats()
+    ctx.sync()
+    assert np.all(r["n_p2p"].cpu().numpy() == 2999) and np.all(r["n_mono"].cpu().numpy() == 0)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert rel_rms(r["acc"].cpu().numpy(), d["acc"]) <= tol
+
+
+def test_forces_plain_equals_stats_variant(ctx):
+    s = icgen.plummer(4096, 1)
+    for prec in ("fp64", "fp32"):
+        t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.5, 0.01, precision=prec)).upward()
+        a = t.forces()
+        r = t.forces_stats()
+        ctx.sync()
+        assert torch.equal(a, r["acc"])
