@@ -68,7 +68,9 @@ typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
  *            opening decisions are certified against the FP64 test (re-evaluated in
  *            FP64 when the FP32 value is within its rounding bound of the threshold),
  *            so the interaction sets are those of the FP64 method.
- *  flags     reserved, pass 0. */
+ *  flags     0, or for server requests BH_REQ_RELEASE: free the request's state when it
+ *            completes (its energies stay available; bh_server_fetch is then refused). */
+#define BH_REQ_RELEASE 1u
 typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;

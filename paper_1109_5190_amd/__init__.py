@@ -81,6 +81,13 @@ _SIGS = {
     "bh_forest_energy": ([_VP, _VP, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_destroy": ([_VP, _VP], C.c_int),
     "bh_ic_generate": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP], C.c_int),
+    "bh_server_create": ([_VP, _VP, C.c_size_t, C.c_int32, C.c_int64, C.POINTER(_VP)], C.c_int),
+    "bh_server_submit": ([_VP, C.POINTER(Request), C.POINTER(C.c_uint64)], C.c_int),
+    "bh_server_poll": ([_VP, C.c_uint64, C.POINTER(Result)], C.c_int),
+    "bh_server_fetch": ([_VP, C.c_uint64, _VP, _VP], C.c_int),
+    "bh_server_cancel": ([_VP, C.c_uint64], C.c_int),
+    "bh_server_now": ([_VP], C.c_double),
+    "bh_server_destroy": ([_VP], C.c_int),
 }
 
 _lib = None
@@ -340,6 +347,61 @@ class Forest:
     def close(self):
         if getattr(self, "h", None):
             lib().bh_forest_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+REQ_RELEASE = 1
+STATE_NAMES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+
+class Server:
+    """bh_server: continuous batching of simulation requests on its own thread and stream."""
+
+    def __init__(self, ctx: Context, arena_bytes, max_slots=64, max_resident=1 << 24):
+        self.ctx = ctx
+        self._raw, self.arena = workspace(int(arena_bytes), ctx.device)
+        h = _VP()
+        _check(lib().bh_server_create(ctx.h, _ptr(self.arena), int(arena_bytes), int(max_slots), int(max_resident),
+                                      C.byref(h)))
+        self.h = h
+
+    def submit(self, n, steps, ic_kind, seed, p: Params, dt, release=False):
+        pp = Params(p.theta, p.eps, p.G, p.leaf_cap, p.precision, (p.flags | REQ_RELEASE) if release else p.flags, 0)
+        r = Request(int(n), int(steps), int(ic_kind), int(seed) & 0xFFFFFFFFFFFFFFFF, pp, float(dt))
+        rid = C.c_uint64()
+        _check(lib().bh_server_submit(self.h, C.byref(r), C.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, rid):
+        res = Result()
+        st = lib().bh_server_poll(self.h, C.c_uint64(rid), C.byref(res))
+        if st not in (OK, E_BUSY, E_CANCELLED, E_DEVICE):
+            _check(st)
+        return dict(state=STATE_NAMES.get(res.state, res.state), steps_done=res.steps_done, t_submit=res.t_submit,
+                    t_admit=res.t_admit, t_done=res.t_done, K=res.K, W=res.W)
+
+    def fetch(self, rid, n):
+        torch = _torch()
+        pos = torch.empty((n, 3), dtype=torch.float64, device=self.ctx.device)
+        vel = torch.empty((n, 3), dtype=torch.float64, device=self.ctx.device)
+        _check(lib().bh_server_fetch(self.h, C.c_uint64(rid), _ptr(pos), _ptr(vel)))
+        return pos, vel
+
+    def cancel(self, rid):
+        _check(lib().bh_server_cancel(self.h, C.c_uint64(rid)))
+
+    def now(self):
+        return float(lib().bh_server_now(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bh_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -56,12 +56,14 @@ struct Carver {
 
 }  // namespace
 
-// Lays out a forest in `ws` (or only measures it when ws == NULL).  Returns the bytes needed.
-size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws) {
+// Host tables of a forest membership: segment descriptors (state pointers left
+// null: the concatenated arrays are passed to each launch), sort tiles and walk groups.
+void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p) {
     F.seg.assign(nseg, SegDesc{});
     F.tiles.clear();
     F.groups.clear();
     uint64_t ntot = 0;
+    bool has32 = false, has64 = false;
     for (int32_t s = 0; s < nseg; ++s) {
         SegDesc &d = F.seg[s];
         d.start = (uint32_t)ntot;
@@ -76,6 +78,7 @@ size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.eps = p[s].eps;
         d.G = p[s].G;
         d.dt = 0.0;
+        (p[s].precision == BH_FP32 ? has32 : has64) = true;
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;
             uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);
@@ -88,27 +91,45 @@ size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         }
         ntot += (uint64_t)n[s];
     }
-    F.precision = p[0].precision;
     ForestDev &D = F.dev;
-    D = ForestDev{};
     D.nseg = (uint32_t)nseg;
     D.ntot = (uint32_t)ntot;
     D.ntiles = (uint32_t)F.tiles.size();
     D.ngroups = (uint32_t)F.groups.size();
     D.mcap = (uint32_t)(2 * ntot);
-    const size_t N = ntot, Mc = D.mcap;
-    size_t scan_len = std::max<size_t>(std::max<size_t>(256 * (size_t)D.ntiles, N), Mc);
+    D.has32 = has32;
+    D.has64 = has64;
+}
+
+// Capacities that cover the current tables.
+ForestCaps bh_caps_of(const ForestHost &F) {
+    ForestCaps c;
+    c.nseg = F.dev.nseg;
+    c.ntot = F.dev.ntot;
+    c.ntiles = F.dev.ntiles;
+    c.ngroups = F.dev.ngroups;
+    c.fp32 = F.dev.has32 != 0;
+    c.fp64 = F.dev.has64 != 0;
+    return c;
+}
+
+// Lays out the device buffers for capacities `c` in `ws` (or only measures them when
+// ws == NULL).  Returns the bytes needed.  Counts in F.dev are left untouched.
+size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
+    ForestDev &D = F.dev;
+    const size_t N = cap.ntot, Mc = 2 * (size_t)cap.ntot, S = cap.nseg;
+    size_t scan_len = std::max<size_t>(std::max<size_t>(256 * (size_t)cap.ntiles, N), Mc);
     Carver c{ws};
-    D.seg = c.take<SegDesc>(nseg);
-    D.st = c.take<SegState>(nseg);
-    D.tiles = c.take<TileDesc>(D.ntiles);
-    D.groups = c.take<GroupDesc>(D.ngroups);
+    D.seg = c.take<SegDesc>(S);
+    D.st = c.take<SegState>(S);
+    D.tiles = c.take<TileDesc>(cap.ntiles);
+    D.groups = c.take<GroupDesc>(cap.ngroups);
     D.segid = c.take<uint32_t>(N);
     D.keys = c.take<uint64_t>(N);
     D.keys_alt = c.take<uint64_t>(N);
     D.idx = c.take<uint32_t>(N);
     D.idx_alt = c.take<uint32_t>(N);
-    D.cnt = c.take<uint32_t>(256 * (size_t)D.ntiles + 1);
+    D.cnt = c.take<uint32_t>(256 * (size_t)cap.ntiles + 1);
     D.scan_tmp = c.take<uint32_t>(scan_len / 2048 + 2);
     D.spos = c.take<double>(3 * N);
     D.smass = c.take<double>(N);
@@ -130,17 +151,21 @@ size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
     D.level_list = c.take<uint32_t>(N + 1);
     D.nM = c.take<double>(Mc);
     D.nS = c.take<double>(3 * Mc);
-    bool any32 = false, any64 = false;
-    for (int32_t s = 0; s < nseg; ++s) (p[s].precision == BH_FP32 ? any32 : any64) = true;
-    D.w32 = any32 ? c.take<WRec32>(Mc) : nullptr;
-    D.w64 = any64 ? c.take<WRec64>(Mc) : nullptr;
+    D.w32 = cap.fp32 ? c.take<WRec32>(Mc) : nullptr;
+    D.w64 = cap.fp64 ? c.take<WRec64>(Mc) : nullptr;
     D.err = c.take<uint32_t>(64);
     D.stats = c.take<unsigned long long>(8);
-    D.red = c.take<double>(2 * (size_t)nseg);
+    D.red = c.take<double>(2 * S);
     D.pot = c.take<double>(N);
+    F.caps = cap;
     F.ws = ws;
     F.ws_bytes = c.off + 256;
     return c.off + 256;
+}
+
+size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws) {
+    bh_forest_tables(F, nseg, n, p);
+    return bh_forest_carve(F, bh_caps_of(F), ws);
 }
 
 static bh_status validate_sizes(int32_t nseg, const int64_t *n, const bh_params *p) {
@@ -151,10 +176,27 @@ static bh_status validate_sizes(int32_t nseg, const int64_t *n, const bh_params 
         if (n[s] < 1) return bh_fail(BH_E_INVAL, "every simulation needs n >= 1");
         bh_status st = bh_check_params(&p[s]);
         if (st != BH_OK) return st;
-        if (p[s].precision != p[0].precision) return bh_fail(BH_E_INVAL, "all simulations of a forest share one precision");
         tot += n[s];
         if (tot > (int64_t)0x3fffffff) return bh_fail(BH_E_INVAL, "too many particles (limit 2^30 - 1 per call)");
     }
+    return BH_OK;
+}
+
+bh_status bh_forest_upload_tables(ForestHost &F) {
+    hipStream_t s = F.ctx->stream;
+    ForestDev &D = F.dev;
+    const ForestCaps &c = F.caps;
+    if (D.nseg > c.nseg || D.ntot > c.ntot || D.ntiles > c.ntiles || D.ngroups > c.ngroups ||
+        (D.has32 && !c.fp32) || (D.has64 && !c.fp64))
+        return bh_fail(BH_E_NOMEM, "forest membership exceeds the planned capacity");
+    HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
+    if (!F.tiles.empty())
+        HIPCHK(hipMemcpyAsync(D.tiles, F.tiles.data(), sizeof(TileDesc) * F.tiles.size(), hipMemcpyHostToDevice, s));
+    if (!F.groups.empty())
+        HIPCHK(hipMemcpyAsync(D.groups, F.groups.data(), sizeof(GroupDesc) * F.groups.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_segid(D, s));
+    // the host tables must outlive the copies
+    HIPCHK(hipStreamSynchronize(s));
     return BH_OK;
 }
 
@@ -166,17 +208,9 @@ bh_status bh_forest_init(bh_ctx *ctx, ForestHost &F, int32_t nseg, const int64_t
     if (ws_bytes < need) return bh_fail(BH_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     bh_plan_forest(F, nseg, n, p, (char *)ws);
     F.ctx = ctx;
-    hipStream_t s = ctx->stream;
-    ForestDev &D = F.dev;
-    HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
-    if (!F.tiles.empty())
-        HIPCHK(hipMemcpyAsync(D.tiles, F.tiles.data(), sizeof(TileDesc) * F.tiles.size(), hipMemcpyHostToDevice, s));
-    if (!F.groups.empty())
-        HIPCHK(hipMemcpyAsync(D.groups, F.groups.data(), sizeof(GroupDesc) * F.groups.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_fill_u32(D.err, 0, 64, s));
-    HIPCHK(launch_fill_u32((uint32_t *)D.stats, 0, 16, s));
-    HIPCHK(launch_segid(D, s));
-    return BH_OK;
+    HIPCHK(launch_fill_u32(F.dev.err, 0, 64, ctx->stream));
+    HIPCHK(launch_fill_u32((uint32_t *)F.dev.stats, 0, 16, ctx->stream));
+    return bh_forest_upload_tables(F);
 }
 
 bh_status bh_forest_upload_seg(ForestHost &F) {
@@ -187,21 +221,22 @@ bh_status bh_forest_upload_seg(ForestHost &F) {
     return BH_OK;
 }
 
-bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot) {
-    hipStream_t s = F.ctx->stream;
+bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot,
+                         bool want_pot, hipStream_t s) {
+    if (!s) s = F.ctx->stream;
     HIPCHK(launch_build(F.dev, pos, mass, s));
     HIPCHK(launch_upward(F.dev, s));
-    HIPCHK(launch_walk(F.dev, F.precision, false, acc, pot, nullptr, nullptr, nullptr, s));
+    HIPCHK(launch_walk(F.dev, false, want_pot, acc, pot, nullptr, nullptr, nullptr, s));
     return BH_OK;
 }
 
-bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc) {
-    hipStream_t s = F.ctx->stream;
-    HIPCHK(launch_kick(F.dev, vel, acc, 0.5, s));
-    HIPCHK(launch_drift(F.dev, pos, vel, s));
-    bh_status st = bh_forest_eval(F, pos, mass, acc, nullptr);
+bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc, hipStream_t s) {
+    if (!s) s = F.ctx->stream;
+    HIPCHK(launch_kick(F.dev, vel, acc, 0, s));
+    HIPCHK(launch_drift(F.dev, pos, vel, 0, s));
+    bh_status st = bh_forest_eval(F, pos, mass, acc, nullptr, false, s);
     if (st != BH_OK) return st;
-    HIPCHK(launch_kick(F.dev, vel, acc, 0.5, s));
+    HIPCHK(launch_kick(F.dev, vel, acc, 0, s));
     return BH_OK;
 }
 
@@ -304,7 +339,7 @@ bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
 bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces");
-    HIPCHK(launch_walk(t->F.dev, t->F.precision, false, acc, pot, nullptr, nullptr, nullptr, ctx->stream));
+    HIPCHK(launch_walk(t->F.dev, false, pot != nullptr, acc, pot, nullptr, nullptr, nullptr, ctx->stream));
     return BH_OK;
 }
 
@@ -313,7 +348,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
     HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
-    HIPCHK(launch_walk(t->F.dev, t->F.precision, true, acc, pot, n_mono, n_p2p, hash, ctx->stream));
+    HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream));
     unsigned long long h[4];
     HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     bh_status st = bh_forest_check_err(t->F);
@@ -386,12 +421,12 @@ bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
         if (st != BH_OK) return st;
     }
     if (!sm->have_acc) {
-        bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, nullptr);
+        bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, nullptr, false, nullptr);
         if (st != BH_OK) return st;
         sm->have_acc = true;
     }
     for (int32_t k = 0; k < nsteps; ++k) {
-        bh_status st = bh_forest_kdk(sm->F, sm->pos, sm->vel, sm->mass, sm->acc);
+        bh_status st = bh_forest_kdk(sm->F, sm->pos, sm->vel, sm->mass, sm->acc, nullptr);
         if (st != BH_OK) return st;
     }
     return BH_OK;
@@ -399,7 +434,7 @@ bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
 
 bh_status bh_energy(bh_ctx *ctx, bh_sim *sm, double out_KW[2]) {
     if (!ctx || !sm || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
-    bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, sm->F.dev.pot);
+    bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, sm->F.dev.pot, true, nullptr);
     if (st != BH_OK) return st;
     sm->have_acc = true;
     HIPCHK(launch_energy(sm->F.dev, sm->vel, sm->mass, sm->F.dev.pot, sm->F.dev.red, ctx->stream));
@@ -471,12 +506,12 @@ bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const doubl
     bh_status st = forest_set_dt(fo, dt);
     if (st != BH_OK) return st;
     if (!fo->have_acc) {
-        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr);
+        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr, false, nullptr);
         if (st != BH_OK) return st;
         fo->have_acc = true;
     }
     for (int32_t k = 0; k < nsteps; ++k) {
-        st = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc);
+        st = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc, nullptr);
         if (st != BH_OK) return st;
     }
     return BH_OK;
@@ -484,7 +519,7 @@ bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const doubl
 
 bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *fo, double *pot) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
-    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, pot);
+    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, pot, pot != nullptr, nullptr);
     if (st == BH_OK) fo->have_acc = true;
     return st;
 }
@@ -495,16 +530,19 @@ bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const
     bh_status st = forest_set_dt(fo, dt);
     if (st != BH_OK) return st;
     if (!fo->have_acc) {
-        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr);
+        st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, nullptr, false, nullptr);
         if (st != BH_OK) return st;
         fo->have_acc = true;
     }
+    // a graph is recorded on a private stream (the caller's stream may be the null
+    // stream, which cannot be captured) and replayed on the caller's stream
     hipStream_t s = ctx->stream;
     if (!fo->graph) {
+        if (!fo->cap_stream) HIPCHK(hipStreamCreateWithFlags(&fo->cap_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        bh_status cst = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc);
-        hipError_t ee = hipStreamEndCapture(s, &g);
+        HIPCHK(hipStreamBeginCapture(fo->cap_stream, hipStreamCaptureModeThreadLocal));
+        bh_status cst = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc, fo->cap_stream);
+        hipError_t ee = hipStreamEndCapture(fo->cap_stream, &g);
         if (cst != BH_OK) {
             if (g) (void)hipGraphDestroy(g);
             return cst;
@@ -522,13 +560,14 @@ bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *fo) {
     (void)ctx;
     if (!fo) return BH_OK;
     if (fo->graph) (void)hipGraphExecDestroy(fo->graph);
+    if (fo->cap_stream) (void)hipStreamDestroy(fo->cap_stream);
     delete fo;
     return BH_OK;
 }
 
 bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *fo, double *out_KW) {
     if (!ctx || !fo || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
-    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, fo->F.dev.pot);
+    bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, fo->F.dev.pot, true, nullptr);
     if (st != BH_OK) return st;
     fo->have_acc = true;
     HIPCHK(launch_energy(fo->F.dev, fo->vel, fo->mass, fo->F.dev.pot, fo->F.dev.red, ctx->stream));

@@ -155,12 +155,15 @@ __global__ void k_seg_reset(ForestDev f) {
 
 __global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos) {
     const TileDesc td = f.tiles[blockIdx.x];
+    const SegDesc &sd = f.seg[td.seg];
+    const double *pb = seg_base(pos, sd.pos, sd, 3);
+    const uint32_t j0 = td.start - sd.start;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
-        size_t i = (size_t)td.start + j;
+        size_t i = (size_t)j0 + j;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double v = pos[3 * i + d];
+            double v = pb[3 * i + d];
             mn[d] = fmin(mn[d], v);
             mx[d] = fmax(mx[d], v);
         }
@@ -210,12 +213,15 @@ __global__ void __launch_bounds__(kTileThreads) k_keys(ForestDev f, const double
     }
     __syncthreads();
     const double scale = scale_s;
+    const SegDesc &sd = f.seg[td.seg];
+    const double *pb = seg_base(pos, sd.pos, sd, 3);
+    const uint32_t j0 = td.start - sd.start;
     for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
         size_t i = (size_t)td.start + j;
         uint64_t q[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double c = floor(__dmul_rn(__dsub_rn(pos[3 * i + d], lo_s[d]), scale));
+            double c = floor(__dmul_rn(__dsub_rn(pb[3 * ((size_t)j0 + j) + d], lo_s[d]), scale));
             c = fmin(fmax(c, 0.0), 2097151.0);
             q[d] = (uint64_t)c;
         }
@@ -338,9 +344,12 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, cons
 __global__ void k_permute(ForestDev f, const double *pos, const double *mass) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= f.ntot) return;
-    uint32_t i = f.idx[r];
-    double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
-    double m = mass[i];
+    const SegDesc &sd = f.seg[f.segid[r]];
+    const size_t li = f.idx[r] - sd.start;
+    const double *pb = seg_base(pos, sd.pos, sd, 3);
+    const double *mb = seg_base(mass, sd.mass, sd, 1);
+    double x = pb[3 * li], y = pb[3 * li + 1], z = pb[3 * li + 2];
+    double m = mb[li];
     f.spos[3 * (size_t)r] = x;
     f.spos[3 * (size_t)r + 1] = y;
     f.spos[3 * (size_t)r + 2] = z;

@@ -21,15 +21,22 @@ constexpr uint32_t kErrStack = 1u;
 constexpr uint32_t kErrNonFinite = 2u;
 constexpr uint32_t kErrTree = 4u;      // inconsistent tree: the walk is skipped
 
-// Per simulation, fixed at forest creation (host written).
+// Per simulation, fixed while its membership in a forest lasts (host written).
 struct SegDesc {
-    uint32_t start, n;          // particle rows [start, start + n) of the concatenated arrays
+    uint32_t start, n;          // rows [start, start + n) of the forest's sorted/concatenated index space
     uint32_t tile_base, ntiles; // sort tiles of this simulation
     uint32_t group_base, ngroups;
     int32_t leaf_cap, precision;
     double theta, eps, G;
     double dt;
+    // this simulation's state, indexed 0..n-1 (used when a launch is given no concatenated arrays)
+    const double *pos, *mass;
+    double *vel, *acc, *pot;
+    uint32_t phase;             // kPhase* bits: which parts of a step apply this iteration
+    uint32_t pad;
 };
+
+constexpr uint32_t kPhaseDrift = 1u, kPhaseKick2 = 2u, kPhaseKick1 = 4u;
 
 // Per simulation, written on the device by every build.
 struct SegState {
@@ -72,7 +79,8 @@ struct WRec64 {
 
 // Device-side views of one forest's buffers (all sub-allocated from the caller's workspace).
 struct ForestDev {
-    uint32_t nseg, ntot, ntiles, ngroups, mcap;
+    uint32_t nseg, ntot, ntiles, ngroups, mcap;   // current membership (mcap = 2 ntot)
+    uint32_t has32, has64;                        // precisions present
     SegDesc *seg;
     SegState *st;
     TileDesc *tiles;
@@ -102,6 +110,13 @@ struct ForestDev {
 };
 
 // ---------------------------------------------------------------- helpers ---
+
+// Base of a simulation's rows: the concatenated array shifted to its first row,
+// or the simulation's own array.
+template <typename T>
+__device__ __forceinline__ T *seg_base(T *cat, T *own, const SegDesc &sd, int width) {
+    return cat ? cat + (size_t)width * sd.start : own;
+}
 
 __device__ __forceinline__ unsigned long long ord_enc(double v) {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -183,10 +198,11 @@ __device__ inline uint32_t cell_right(const uint64_t *K, uint32_t r, int level, 
 hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass,
                         hipStream_t s);                          // bbox .. tree topology
 hipError_t launch_upward(const ForestDev &f, hipStream_t s);     // masses, centres, walk records
-hipError_t launch_walk(const ForestDev &f, int precision, bool stats, double *acc, double *pot,
-                       int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, hipStream_t s);
-hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, double half, hipStream_t s);
-hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, hipStream_t s);
+hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s);
+// phase_mask 0: every simulation; else only those whose SegDesc.phase has a bit of the mask.
+hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s);
+hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);
 hipError_t launch_energy(const ForestDev &f, const double *vel, const double *mass, const double *pot,
                          double *out2, hipStream_t s);
 hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,

@@ -11,29 +11,38 @@ namespace bh {
 
 // ------------------------------------------------------------------ KDK ---
 
-__global__ void k_kick(ForestDev f, double *vel, const double *acc, double half) {
-    size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= 3 * (size_t)f.ntot) return;
-    const double h = __dmul_rn(half, f.seg[f.segid[j / 3]].dt);
-    vel[j] = __dadd_rn(vel[j], __dmul_rn(h, acc[j]));
+// One block per tile: the tile's simulation decides (phase) whether this half-kick
+// or drift applies to it in this iteration; phase_mask 0 applies it everywhere.
+__global__ void k_kick(ForestDev f, double *vel, const double *acc, uint32_t phase_mask) {
+    const TileDesc td = f.tiles[blockIdx.x];
+    const SegDesc &sd = f.seg[td.seg];
+    if (phase_mask && !(sd.phase & phase_mask)) return;
+    double *vb = seg_base(vel, sd.vel, sd, 3);
+    const double *ab = seg_base(acc, (const double *)sd.acc, sd, 3);
+    const double h = __dmul_rn(0.5, sd.dt);
+    const size_t j0 = 3 * (size_t)(td.start - sd.start);
+    for (uint32_t j = threadIdx.x; j < 3 * td.count; j += blockDim.x)
+        vb[j0 + j] = __dadd_rn(vb[j0 + j], __dmul_rn(h, ab[j0 + j]));
 }
 
-__global__ void k_drift(ForestDev f, double *pos, const double *vel) {
-    size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= 3 * (size_t)f.ntot) return;
-    const double dt = f.seg[f.segid[j / 3]].dt;
-    pos[j] = __dadd_rn(pos[j], __dmul_rn(dt, vel[j]));
+__global__ void k_drift(ForestDev f, double *pos, const double *vel, uint32_t phase_mask) {
+    const TileDesc td = f.tiles[blockIdx.x];
+    const SegDesc &sd = f.seg[td.seg];
+    if (phase_mask && !(sd.phase & phase_mask)) return;
+    double *pb = seg_base(pos, (double *)sd.pos, sd, 3);
+    const double *vb = seg_base(vel, (const double *)sd.vel, sd, 3);
+    const size_t j0 = 3 * (size_t)(td.start - sd.start);
+    for (uint32_t j = threadIdx.x; j < 3 * td.count; j += blockDim.x)
+        pb[j0 + j] = __dadd_rn(pb[j0 + j], __dmul_rn(sd.dt, vb[j0 + j]));
 }
 
-hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, double half, hipStream_t s) {
-    const size_t n = 3 * (size_t)f.ntot;
-    hipLaunchKernelGGL(k_kick, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, vel, acc, half);
+hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s) {
+    if (f.ntiles) hipLaunchKernelGGL(k_kick, dim3(f.ntiles), dim3(256), 0, s, f, vel, acc, phase_mask);
     return hipGetLastError();
 }
 
-hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, hipStream_t s) {
-    const size_t n = 3 * (size_t)f.ntot;
-    hipLaunchKernelGGL(k_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, pos, vel);
+hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s) {
+    if (f.ntiles) hipLaunchKernelGGL(k_drift, dim3(f.ntiles), dim3(256), 0, s, f, pos, vel, phase_mask);
     return hipGetLastError();
 }
 
@@ -45,11 +54,14 @@ __global__ void __launch_bounds__(256) k_energy(ForestDev f, const double *vel, 
                                                 double *out) {
     __shared__ double sk[256], sw[256];
     const SegDesc &sd = f.seg[blockIdx.x];
+    const double *vb = seg_base(vel, (const double *)sd.vel, sd, 3);
+    const double *mb = seg_base(mass, sd.mass, sd, 1);
+    const double *pb = seg_base(pot, (const double *)sd.pot, sd, 1);
     double K = 0.0, W = 0.0;
-    for (uint32_t i = sd.start + threadIdx.x; i < sd.start + sd.n; i += 256) {
-        const double *v = vel + 3 * (size_t)i;
-        K += mass[i] * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-        if (pot) W += mass[i] * pot[i];
+    for (uint32_t i = threadIdx.x; i < sd.n; i += 256) {
+        const double *v = vb + 3 * (size_t)i;
+        K += mb[i] * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        if (pb) W += mb[i] * pb[i];
     }
     sk[threadIdx.x] = K;
     sw[threadIdx.x] = W;

@@ -12,12 +12,17 @@ struct bh_ctx {
     double *scratch = nullptr;   // initial-condition reductions (6 x 256 doubles) + fault flag
 };
 
+struct ForestCaps {
+    uint32_t nseg = 0, ntot = 0, ntiles = 0, ngroups = 0;
+    bool fp32 = false, fp64 = false;
+};
+
 struct ForestHost {
     bh::ForestDev dev{};
     std::vector<bh::SegDesc> seg;
     std::vector<bh::TileDesc> tiles;
     std::vector<bh::GroupDesc> groups;
-    int precision = 0;
+    ForestCaps caps;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bh_ctx *ctx = nullptr;
@@ -43,14 +48,21 @@ struct bh_forest {
     const double *mass = nullptr;
     bool have_acc = false;
     hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream the step graph is recorded on
 };
 
 bh_status bh_fail(bh_status st, const std::string &msg);
 bh_status bh_check_params(const bh_params *p);
 size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws);
+void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p);
+ForestCaps bh_caps_of(const ForestHost &F);
+size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws);
+bh_status bh_forest_upload_tables(ForestHost &F);
 bh_status bh_forest_init(bh_ctx *ctx, ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, void *ws,
                          size_t ws_bytes);
 bh_status bh_forest_upload_seg(ForestHost &F);
-bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot);
-bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc);
+// s == NULL: the context's stream
+bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot,
+                         bool want_pot, hipStream_t s);
+bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc, hipStream_t s);
 bh_status bh_forest_check_err(ForestHost &F);

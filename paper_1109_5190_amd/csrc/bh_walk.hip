@@ -103,6 +103,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 1) return;
     const SegState &st = f.st[sid];
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gd.start + (live ? (uint32_t)lane : 0u);
@@ -253,11 +254,16 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
     fold();
     if (live) {
         const uint32_t i = f.idx[r];
+        const size_t li = i - sd.start;
         const double G = sd.G;
-        out.acc[3 * (size_t)i] = G * ((double)sx - (double)cx);
-        out.acc[3 * (size_t)i + 1] = G * ((double)sy - (double)cy);
-        out.acc[3 * (size_t)i + 2] = G * ((double)sz - (double)cz);
-        if (POT && out.pot) out.pot[i] = G * ((double)sp_ - (double)cp);
+        double *accb = seg_base(out.acc, sd.acc, sd, 3);
+        accb[3 * li] = G * ((double)sx - (double)cx);
+        accb[3 * li + 1] = G * ((double)sy - (double)cy);
+        accb[3 * li + 2] = G * ((double)sz - (double)cz);
+        if (POT) {
+            double *potb = seg_base(out.pot, sd.pot, sd, 1);
+            if (potb) potb[li] = G * ((double)sp_ - (double)cp);
+        }
         if (STATS) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
@@ -288,6 +294,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 0) return;
     const SegState &st = f.st[sid];
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gd.start + (live ? (uint32_t)lane : 0u);
@@ -370,11 +377,16 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
     }
     if (live) {
         const uint32_t i = f.idx[r];
+        const size_t li = i - sd.start;
         const double G = sd.G;
-        out.acc[3 * (size_t)i] = G * ax;
-        out.acc[3 * (size_t)i + 1] = G * ay;
-        out.acc[3 * (size_t)i + 2] = G * az;
-        if (POT && out.pot) out.pot[i] = G * ap;
+        double *accb = seg_base(out.acc, sd.acc, sd, 3);
+        accb[3 * li] = G * ax;
+        accb[3 * li + 1] = G * ay;
+        accb[3 * li + 2] = G * az;
+        if (POT) {
+            double *potb = seg_base(out.pot, sd.pot, sd, 1);
+            if (potb) potb[li] = G * ap;
+        }
         if (STATS) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
@@ -392,27 +404,28 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
     }
 }
 
-hipError_t launch_walk(const ForestDev &f, int precision, bool stats, double *acc, double *pot, int64_t *n_mono,
+hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, hipStream_t s) {
     WalkOut o{acc, pot, n_mono, n_p2p, hash};
     const unsigned blocks = (f.ngroups + (kWalkThreads / 64) - 1) / (kWalkThreads / 64);
     if (blocks == 0) return hipSuccess;
-    const bool P = pot != nullptr;
-    if (precision == 1) {
+    const dim3 g(blocks), b(kWalkThreads);
+    if (f.has32) {
         if (stats) {
-            if (P) hipLaunchKernelGGL((k_walk32<true, true>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<true, false>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk32<true, true>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk32<true, false>), g, b, 0, s, f, o);
         } else {
-            if (P) hipLaunchKernelGGL((k_walk32<false, true>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<false, false>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk32<false, true>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk32<false, false>), g, b, 0, s, f, o);
         }
-    } else {
+    }
+    if (f.has64) {
         if (stats) {
-            if (P) hipLaunchKernelGGL((k_walk64<true, true>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<true, false>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk64<true, true>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk64<true, false>), g, b, 0, s, f, o);
         } else {
-            if (P) hipLaunchKernelGGL((k_walk64<false, true>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<false, false>), dim3(blocks), dim3(kWalkThreads), 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk64<false, true>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk64<false, false>), g, b, 0, s, f, o);
         }
     }
     return hipGetLastError();
