@@ -47,7 +47,50 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=262144, help="oracle walk targets for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-precision", default="fp32")
     return ap.parse_args()
+
+
+def serve(a, bh, ctx, torch):
+    """Serving leg: Poisson arrivals of simulation requests through the continuous-batching server."""
+    import numpy as np
+
+    import icgen
+    reqs = icgen.request_stream(a.serve_requests, a.serve_rate, master_seed=7)
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(48 << 30, free * 0.6))
+    sv = bh.Server(ctx, arena, max_slots=64, max_resident=1 << 24)
+    p = bh.params(0.5, 0.01, 1.0, 1, a.serve_precision)
+    t0 = sv.now()
+    ids = []
+    for r in reqs:
+        while sv.now() - t0 < r["t"]:
+            time.sleep(min(0.001, max(0.0, r["t"] - (sv.now() - t0))))
+        ids.append(sv.submit(r["n"], r["steps"], r["kind"], r["seed"], p, 1e-3, release=True))
+    done = []
+    for rid in ids:
+        while True:
+            st = sv.poll(rid)
+            if st["state"] in ("done", "failed", "cancelled"):
+                break
+            time.sleep(0.002)
+        done.append(st)
+    sv.close()
+    ok = [d for d in done if d["state"] == "done"]
+    lat = np.array([d["t_done"] - d["t_submit"] for d in ok])
+    wait = np.array([d["t_admit"] - d["t_submit"] for d in ok])
+    work = sum(r["n"] * r["steps"] for r, d in zip(reqs, done) if d["state"] == "done")
+    span = max(d["t_done"] for d in ok) - min(d["t_submit"] for d in ok)
+    offered = a.serve_rate * float(np.mean([r["n"] * r["steps"] for r in reqs]))
+    return {"requests": len(reqs), "completed": len(ok), "rate_req_per_s": a.serve_rate,
+            "precision": a.serve_precision, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_queue_wait_s": float(wait.mean()),
+            "throughput_particle_steps_per_s": work / span, "offered_particle_steps_per_s": offered,
+            "makespan_s": span, "arena_bytes": arena, "max_slots": 64, "max_resident": 1 << 24,
+            "workload": "Poisson arrivals, N log-uniform in [4096, 4194304], steps uniform 1..100, "
+                        "Plummer or cube 50/50, theta=0.5, eps=0.01, dt=1e-3, seed 7"}
 
 
 def main():
@@ -159,6 +202,11 @@ def main():
                      "build_upward_ms": rr["ms_build_upward"],
                      "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s",
                                   "frac": ach / pk}}
+
+    if a.serve_requests > 0:
+        out["serving"] = serve(a, bh, ctx, torch)
+        print(f"# serving: p50 {out['serving']['p50_latency_s']:.3f}s p99 {out['serving']['p99_latency_s']:.3f}s",
+              file=sys.stderr, flush=True)
 
     if not a.no_cpu:
         import oracle
