@@ -158,6 +158,8 @@ def main():
         inter = int(tot["n_mono"] + tot["n_p2p"])
         results[prec] = dict(ms_per_step=ms_step, ms_walk=ms_walk, ms_build_upward=ms_build,
                              interactions=inter, visits=int(tot["n_visits"]), fallbacks=int(tot["n_fallback"]),
+                             wave_visits=int(tot["wave_visits"]), wave_entries=int(tot["wave_entries"]),
+                             wave_accepts=int(tot["wave_accepts"]), wave_leaves=int(tot["wave_leaves"]),
                              acc=st["acc"].cpu().numpy())
         print(f"# {prec}: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, build+upward {ms_build:.3f} ms, "
               f"{inter / a.n:.1f} interactions/particle", file=sys.stderr, flush=True)
@@ -189,7 +191,10 @@ def main():
                                f"per launch / {r['ms_walk']:.3f} ms)"},
         "walk_only": {"ms": r["ms_walk"], "mparticles_per_s": a.n / (r["ms_walk"] * 1e-3) / 1e6,
                       "interactions_per_particle": r["interactions"] / a.n,
-                      "fp64_fallback_tests": r["fallbacks"], "opening_tests": r["visits"]},
+                      "fp64_fallback_tests": r["fallbacks"], "opening_tests": r["visits"],
+                      "wave_visits": r["wave_visits"], "wave_entries": r["wave_entries"],
+                      "wave_accepts": r["wave_accepts"], "wave_leaves": r["wave_leaves"],
+                      "lane_utilisation": r["interactions"] / max(1, 64 * r["wave_visits"])},
         "build_upward_ms": r["ms_build_upward"],
     }
     for prec, rr in results.items():

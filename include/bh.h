@@ -85,6 +85,9 @@ typedef struct {
     uint64_t n_p2p;       /* body-body interactions in opened leaves, self excluded */
     uint64_t n_visits;    /* (cube, body) opening tests */
     uint64_t n_fallback;  /* FP32 opening tests re-evaluated in FP64 */
+    /* wavefront-level diagnostics (FP32 mode; 0 in FP64 mode): cube visits, popped
+     * stack entries, visits where at least one lane accepted, opened leaves */
+    uint64_t wave_visits, wave_entries, wave_accepts, wave_leaves;
 } bh_stats;
 
 typedef struct bh_ctx bh_ctx;

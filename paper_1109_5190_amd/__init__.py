@@ -38,7 +38,8 @@ def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64") -> Params:
 
 class Stats(C.Structure):
     _fields_ = [("n_mono", C.c_uint64), ("n_p2p", C.c_uint64), ("n_visits", C.c_uint64),
-                ("n_fallback", C.c_uint64)]
+                ("n_fallback", C.c_uint64), ("wave_visits", C.c_uint64), ("wave_entries", C.c_uint64),
+                ("wave_accepts", C.c_uint64), ("wave_leaves", C.c_uint64)]
 
 
 class Request(C.Structure):
@@ -217,7 +218,7 @@ class Tree:
         _check(lib().bh_forces_stats(self.ctx.h, self.h, _ptr(acc), _ptr(ph), _ptr(nm), _ptr(np_), _ptr(hs),
                                      C.byref(st)))
         return dict(acc=acc, pot=ph, n_mono=nm, n_p2p=np_, hash=hs,
-                    totals=dict(n_mono=st.n_mono, n_p2p=st.n_p2p, n_visits=st.n_visits, n_fallback=st.n_fallback))
+                    totals={k: int(getattr(st, k)) for k, _ in Stats._fields_})
 
     def info(self):
         nn = C.c_int64()

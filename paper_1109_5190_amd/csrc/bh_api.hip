@@ -130,6 +130,8 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.idx = c.take<uint32_t>(N);
     D.idx_alt = c.take<uint32_t>(N);
     D.cnt = c.take<uint32_t>(256 * (size_t)cap.ntiles + 1);
+    D.segtot = c.take<uint32_t>(256 * S);
+    D.segp = c.take<uint32_t>(256 * S);
     D.scan_tmp = c.take<uint32_t>(scan_len / 2048 + 2);
     D.spos = c.take<double>(3 * N);
     D.smass = c.take<double>(N);
@@ -145,10 +147,7 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.cs = c.take<uint32_t>(Mc + 1);
     D.slot_of = c.take<uint32_t>(Mc);
     D.node_at_slot = c.take<uint32_t>(Mc);
-    D.level_cnt = c.take<uint32_t>(32);
-    D.level_off = c.take<uint32_t>(32);
-    D.level_cur = c.take<uint32_t>(32);
-    D.level_list = c.take<uint32_t>(N + 1);
+    D.tile_mm = c.take<unsigned long long>(6 * (size_t)cap.ntiles);
     D.nM = c.take<double>(Mc);
     D.nS = c.take<double>(3 * Mc);
     D.w32 = cap.fp32 ? c.take<WRec32>(Mc) : nullptr;
@@ -349,7 +348,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
     HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
     HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream));
-    unsigned long long h[4];
+    unsigned long long h[8];
     HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     bh_status st = bh_forest_check_err(t->F);
     if (st != BH_OK) return st;
@@ -358,6 +357,10 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
         totals->n_p2p = h[1];
         totals->n_visits = h[2];
         totals->n_fallback = h[3];
+        totals->wave_visits = h[4];
+        totals->wave_entries = h[5];
+        totals->wave_accepts = h[6];
+        totals->wave_leaves = h[7];
     }
     return BH_OK;
 }

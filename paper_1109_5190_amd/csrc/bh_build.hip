@@ -117,8 +117,49 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t *in, uint32_t 
     }
 }
 
+// One block of 1024 threads for arrays up to kScanSingleMax: each thread scans a
+// contiguous run, then the run totals are scanned across the block.
+constexpr uint32_t kScanSingleMax = 1u << 17;
+
+__global__ void __launch_bounds__(1024) k_scan_single(const uint32_t *in, uint32_t n, uint32_t *out) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t i = b0 + j;
+        if (i < n) s += in[i];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t v = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += wsum[w];
+    uint32_t run = add + v - s;
+    if (threadIdx.x == 1023) out[n] = add + v;
+    __syncthreads();
+    for (uint32_t j = 0; j < per; ++j) {
+        const uint32_t i = b0 + j;
+        if (i < n) {
+            const uint32_t x = in[i];
+            out[i] = run;
+            run += x;
+        }
+    }
+}
+
 static hipError_t scan_exclusive(const uint32_t *in, uint32_t n, uint32_t *out, uint32_t *tmp, int kind,
                                  hipStream_t s) {
+    if (kind == 0 && n <= kScanSingleMax) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, n, out);
+        return hipGetLastError();
+    }
     uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb == 0) nb = 1;
     if (kind == 1) hipLaunchKernelGGL(k_scan_reduce<1>, dim3(nb), dim3(256), 0, s, in, n, tmp);
@@ -143,16 +184,6 @@ hipError_t launch_segid(const ForestDev &f, hipStream_t s) {
 
 // =================================================================== bbox ===
 
-__global__ void k_seg_reset(ForestDev f) {
-    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= f.nseg) return;
-    for (int d = 0; d < 3; ++d) {
-        f.st[s].mn[d] = ~0ull;
-        f.st[s].mx[d] = 0ull;
-    }
-    f.st[s].nn = 0;
-}
-
 __global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos) {
     const TileDesc td = f.tiles[blockIdx.x];
     const SegDesc &sd = f.seg[td.seg];
@@ -175,12 +206,48 @@ __global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double
             mx[d] = fmax(mx[d], __shfl_xor(mx[d], o, 64));
         }
     }
-    if ((threadIdx.x & 63) == 0 && td.count > 0) {
+    __shared__ double wmn[4][3], wmx[4][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int d = 0; d < 3; ++d) { wmn[wave][d] = mn[d]; wmx[wave][d] = mx[d]; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        double a = fmin(fmin(wmn[0][d], wmn[1][d]), fmin(wmn[2][d], wmn[3][d]));
+        double b = fmax(fmax(wmx[0][d], wmx[1][d]), fmax(wmx[2][d], wmx[3][d]));
+        f.tile_mm[6 * (size_t)blockIdx.x + d] = ord_enc(a);
+        f.tile_mm[6 * (size_t)blockIdx.x + 3 + d] = ord_enc(b);
+    }
+}
+
+// Per simulation: min/max over its tiles' partials (integer images: exact, order-free).
+__global__ void __launch_bounds__(256) k_bbox_reduce(ForestDev f) {
+    const SegDesc &sd = f.seg[blockIdx.x];
+    __shared__ unsigned long long red[6][256];
+    unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
+    for (uint32_t t = threadIdx.x; t < sd.ntiles; t += 256) {
+        const unsigned long long *p = f.tile_mm + 6 * (size_t)(sd.tile_base + t);
         for (int d = 0; d < 3; ++d) {
-            atomicMin(&f.st[td.seg].mn[d], ord_enc(mn[d]));
-            atomicMax(&f.st[td.seg].mx[d], ord_enc(mx[d]));
+            v[d] = p[d] < v[d] ? p[d] : v[d];
+            v[3 + d] = p[3 + d] > v[3 + d] ? p[3 + d] : v[3 + d];
         }
     }
+    for (int d = 0; d < 6; ++d) red[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int d = 0; d < 3; ++d) {
+                unsigned long long a = red[d][threadIdx.x + o], b = red[3 + d][threadIdx.x + o];
+                if (a < red[d][threadIdx.x]) red[d][threadIdx.x] = a;
+                if (b > red[3 + d][threadIdx.x]) red[3 + d][threadIdx.x] = b;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        f.st[blockIdx.x].mn[threadIdx.x] = red[threadIdx.x][0];
+        f.st[blockIdx.x].mx[threadIdx.x] = red[3 + threadIdx.x][0];
+    }
+    if (threadIdx.x == 0) f.st[blockIdx.x].nn = 0;
 }
 
 // =================================================================== keys ===
@@ -244,9 +311,6 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dig, uint64_t valid) {
     return peers;
 }
 
-__device__ __forceinline__ uint32_t cnt_index(const SegDesc &sd, uint32_t tile, uint32_t digit) {
-    return 256u * sd.tile_base + digit * sd.ntiles + (tile - sd.tile_base);
-}
 
 __global__ void __launch_bounds__(kTileThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
     __shared__ uint32_t hist[4][256];
@@ -264,9 +328,40 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_hist(ForestDev f, const u
         if (valid && (peers & lt) == 0) hist[wave][dig] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    const SegDesc sd = f.seg[td.seg];
-    uint32_t d = threadIdx.x;
-    f.cnt[cnt_index(sd, blockIdx.x, d)] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+    const uint32_t d = threadIdx.x;
+    f.cnt[256u * blockIdx.x + d] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+}
+
+// Digit d (one block per digit): exclusive scan of the tile counts over the tiles of
+// each simulation (tiles of a simulation are contiguous), in place; the
+// simulation's total of digit d goes to segtot[seg][d].
+__global__ void __launch_bounds__(256) k_sort_colscan(ForestDev f) {
+    __shared__ uint32_t w[4];
+    __shared__ uint32_t last;
+    const uint32_t d = blockIdx.x;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < f.ntiles; c0 += 256) {
+        const uint32_t j = c0 + threadIdx.x;
+        const bool ok = j < f.ntiles;
+        const uint32_t v = ok ? f.cnt[256u * j + d] : 0u;
+        const uint32_t incl = block_inclusive_scan_256(v, w) + carry;
+        const uint32_t excl = incl - v;
+        uint32_t sid = 0;
+        if (ok) {
+            sid = f.tiles[j].seg;
+            if (j == f.seg[sid].tile_base) f.segp[256u * sid + d] = excl;
+        }
+        if (threadIdx.x == 255) last = incl;
+        __syncthreads();
+        if (ok) {
+            const SegDesc &sd = f.seg[sid];
+            const uint32_t b = f.segp[256u * sid + d];
+            f.cnt[256u * j + d] = excl - b;
+            if (j == sd.tile_base + sd.ntiles - 1) f.segtot[256u * sid + d] = incl - b;
+        }
+        carry = last;
+        __syncthreads();
+    }
 }
 
 __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
@@ -315,8 +410,10 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, cons
         whist[1][d] = c0;
         whist[2][d] = c0 + c1;
         whist[3][d] = c0 + c1 + c2;
-        const SegDesc sd = f.seg[td.seg];
-        gbase[d] = f.cnt[cnt_index(sd, blockIdx.x, d)];
+        const SegDesc &sd = f.seg[td.seg];
+        const uint32_t tot_d = f.segtot[256u * td.seg + d];
+        const uint32_t dinc = block_inclusive_scan_256(tot_d, wtot);
+        gbase[d] = sd.start + (dinc - tot_d) + f.cnt[256u * blockIdx.x + d];
     }
     __syncthreads();
 #pragma unroll
@@ -416,9 +513,6 @@ __device__ __forceinline__ uint32_t node_id(const ForestDev &f, uint32_t first, 
 
 // Mark pass: every node sets bit `level` of mask[first].
 __global__ void __launch_bounds__(256) k_mark(ForestDev f) {
-    __shared__ uint32_t lcount[32];
-    if (threadIdx.x < 32) lcount[threadIdx.x] = 0;
-    __syncthreads();
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < f.ntot) {
         const Seg sg = seg_of(f, r);
@@ -432,36 +526,15 @@ __global__ void __launch_bounds__(256) k_mark(ForestDev f) {
             uint32_t q = cell_left(f.keys, r - 1, l + 1, sg.lo);
             if (q == sg.lo || f.lcp[q] < l) {
                 uint32_t R = cell_right(f.keys, r, l, sg.hi);
-                if (R - q > sg.cap) {
-                    atomicOr(&f.mask[q], 1u << l);
-                    atomicAdd(&lcount[l], 1u);
-                }
+                if (R - q > sg.cap) atomicOr(&f.mask[q], 1u << l);
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x < kMaxLevel && lcount[threadIdx.x]) atomicAdd(&f.level_cnt[threadIdx.x], lcount[threadIdx.x]);
 }
 
-__global__ void k_level_offsets(ForestDev f) {
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int l = 0; l < 32; ++l) {
-            f.level_off[l] = run;
-            run += f.level_cnt[l];
-            f.level_cur[l] = 0;
-        }
-    }
-}
-
-// Fill pass: node records at their preorder ids, child links, level buckets.
+// Fill pass: node records at their preorder ids and child links.
 __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
-    __shared__ uint32_t lcount[32], lbase[32];
-    if (threadIdx.x < 32) lcount[threadIdx.x] = 0;
-    __syncthreads();
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    int my_level = -1;
-    uint32_t my_node = 0, my_off = 0;
     if (r < f.ntot) {
         const uint32_t s = f.segid[r];
         const Seg sg = seg_of(f, r);
@@ -506,20 +579,9 @@ __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
                         c0 = c1;
                     }
                     f.nchild[g] = k;
-                    my_level = l;
-                    my_node = g;
-                    my_off = atomicAdd(&lcount[l], 1u);
                 }
             }
         }
-    }
-    __syncthreads();
-    if (threadIdx.x < kMaxLevel) lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&f.level_cur[threadIdx.x], lcount[threadIdx.x]) : 0;
-    __syncthreads();
-    if (my_level >= 0) {
-        uint32_t at = f.level_off[my_level] + lbase[my_level] + my_off;
-        if (at <= f.ntot) f.level_list[at] = my_node;
-        else atomicOr(f.err, kErrTree);
     }
 }
 
@@ -553,18 +615,16 @@ __global__ void k_seg_nodes(ForestDev f) {
 
 hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass, hipStream_t s) {
     const unsigned segb = (f.nseg + 255) / 256;
-    hipLaunchKernelGGL(k_seg_reset, dim3(segb), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
+    hipLaunchKernelGGL(k_bbox_reduce, dim3(f.nseg), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
     // 8 stable passes of 8 bits: the result returns to (keys, idx)
-    const uint32_t ncnt = 256u * f.ntiles;
     uint64_t *kin = f.keys, *kout = f.keys_alt;
     uint32_t *iin = f.idx, *iout = f.idx_alt;
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, shift);
-        hipError_t e = scan_exclusive(f.cnt, ncnt, f.cnt, f.scan_tmp, 0, s);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_colscan, dim3(256), dim3(256), 0, s, f);
         hipLaunchKernelGGL(k_sort_scatter, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, iin, kout, iout, shift);
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
@@ -572,12 +632,9 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
     const unsigned nb = (f.ntot + 255) / 256;
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, s, f, pos, mass);
     hipLaunchKernelGGL(k_lcp, dim3((f.ntot + 1 + 255) / 256), dim3(256), 0, s, f);
-    hipError_t e = launch_fill_u32(f.level_cnt, 0, 32, s);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mark, dim3(nb), dim3(256), 0, s, f);
-    e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);
+    hipError_t e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, f);
     e = launch_fill_u32(f.nchild, 0, f.mcap, s);
     if (e != hipSuccess) return e;
     e = launch_fill_u32(f.nparent, kNone, f.mcap, s);
@@ -596,15 +653,20 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
 
 // ================================================================= upward ===
 
+// Upward pass, level by level from the deepest level: a launch sums the leaves
+// (particles in key order), then one launch per level sums each internal node's
+// children in octant order.  The kernel boundaries order the levels; no
+// device-scope fences are needed.
+
 __global__ void k_up_leaf(ForestDev f) {
-    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t mtot = f.base[f.ntot];
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mtot = f.base[f.ntot];
     if (g >= mtot || f.nchild[g] != 0) return;
-    uint32_t a = f.nfirst[g], b = a + f.ncount[g];
+    const uint32_t a = f.nfirst[g], b = a + f.ncount[g];
     if (a >= f.ntot || b > f.ntot || b <= a) { atomicOr(f.err, kErrTree); return; }
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     for (uint32_t r = a; r < b; ++r) {
-        double m = f.smass[r];
+        const double m = f.smass[r];
         M = __dadd_rn(M, m);
         Sx = __dadd_rn(Sx, __dmul_rn(m, f.spos[3 * (size_t)r]));
         Sy = __dadd_rn(Sy, __dmul_rn(m, f.spos[3 * (size_t)r + 1]));
@@ -617,24 +679,22 @@ __global__ void k_up_leaf(ForestDev f) {
 }
 
 __global__ void k_up_level(ForestDev f, int level) {
-    const uint32_t n = f.level_cnt[level], off = f.level_off[level];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t g = f.level_list[off + i];
-        const uint32_t mtot = f.base[f.ntot];
-        if (g >= mtot) { atomicOr(f.err, kErrTree); continue; }
-        uint32_t c0 = f.nseg + f.cs[g], nc = f.nchild[g];
+    const uint32_t mtot = f.base[f.ntot];
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < mtot; g += gridDim.x * blockDim.x) {
+        if (f.nlevel[g] != level || f.nchild[g] == 0) continue;
+        const uint32_t nc = f.nchild[g], c0 = f.nseg + f.cs[g];
         if (nc < 2 || nc > 8 || c0 + nc > mtot) { atomicOr(f.err, kErrTree); continue; }
-        bool bad = false;
-        for (uint32_t k = 0; k < nc; ++k) bad |= f.node_at_slot[c0 + k] >= mtot;
-        if (bad) { atomicOr(f.err, kErrTree); continue; }
         double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+        bool bad = false;
         for (uint32_t k = 0; k < nc; ++k) {
-            uint32_t c = f.node_at_slot[c0 + k];
+            const uint32_t c = f.node_at_slot[c0 + k];
+            if (c >= mtot) { bad = true; break; }
             M = __dadd_rn(M, f.nM[c]);
             Sx = __dadd_rn(Sx, f.nS[3 * (size_t)c]);
             Sy = __dadd_rn(Sy, f.nS[3 * (size_t)c + 1]);
             Sz = __dadd_rn(Sz, f.nS[3 * (size_t)c + 2]);
         }
+        if (bad) { atomicOr(f.err, kErrTree); continue; }
         f.nM[g] = M;
         f.nS[3 * (size_t)g] = Sx;
         f.nS[3 * (size_t)g + 1] = Sy;
@@ -673,15 +733,17 @@ __global__ void k_records(ForestDev f) {
         w.cy = c[1];
         w.cz = c[2];
         w.m = (float)M;
-        // FP32 opening test band (see the walk): exact side^2 when in FP32 range, else always FP64
+        // FP32 opening test constants (see the walk): exact side^2 when in FP32 range, else always FP64
         const int e2 = 2 * (st.k - level);
         const double u = 5.9604644775390625e-8;   // 2^-24
+        const float theta2f = (float)(sd.theta * sd.theta), eps2f = (float)(sd.eps * sd.eps);
         if (e2 > -120 && e2 < 120) {
-            w.S = ldexpf(1.0f, e2);
-            w.band0 = (float)(16.0 * u * ldexp(1.0, e2));
+            const float S = ldexpf(1.0f, e2);
+            w.Sp = fmaf(theta2f, eps2f, S);
+            w.band0 = (float)(16.0 * u * ((double)S + (double)theta2f * (double)eps2f));
             w.band1 = (float)(8.0 * u * s * sd.theta * (1.0 + 1e-6));
         } else {
-            w.S = 0.0f;
+            w.Sp = 0.0f;
             w.band0 = INFINITY;
             w.band1 = 0.0f;
         }
@@ -710,8 +772,7 @@ __global__ void k_records(ForestDev f) {
 hipError_t launch_upward(const ForestDev &f, hipStream_t s) {
     const unsigned mb = (f.mcap + 255) / 256;
     hipLaunchKernelGGL(k_up_leaf, dim3(mb), dim3(256), 0, s, f);
-    unsigned lb = (f.ntot / 2 + 255) / 256;
-    if (lb < 1) lb = 1;
+    unsigned lb = (f.mcap + 255) / 256;
     if (lb > 2048) lb = 2048;
     for (int l = kMaxLevel - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_up_level, dim3(lb), dim3(256), 0, s, f, l);

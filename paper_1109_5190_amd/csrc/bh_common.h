@@ -59,9 +59,9 @@ struct GroupDesc { uint32_t start, count, seg, pad; };
 struct WRec32 {
     double cx, cy, cz;         // centre of mass (FP64)
     float m;                   // mass (FP32)
-    float S;                   // side^2 (exact power of two; 0 if out of FP32 range)
-    float band0;               // rounding band of the FP32 opening test: 16 u S (inf: always FP64)
-    float band1;               // ... plus rho * (band1 + 4 u^2 theta^2 rho), band1 = 8 u s theta
+    float Sp;                  // S' = side^2 + theta^2 eps^2 (FP32)
+    float band0;               // 16 u S' (inf: side^2 outside FP32 range, always decide in FP64)
+    float band1;               // 8 u side theta
     uint32_t link;             // internal: first child slot; leaf: first particle rank
     uint32_t cnt;              // internal: children; leaf: particles | kLeafBit
     uint32_t gid;              // global node id (depth-first preorder)
@@ -88,7 +88,8 @@ struct ForestDev {
     uint32_t *segid;            // per particle row
     uint64_t *keys, *keys_alt;  // sort ping-pong
     uint32_t *idx, *idx_alt;    // idx ends as perm: sorted rank -> original row
-    uint32_t *cnt;              // sort digit counts, 256 per tile (+1 total)
+    uint32_t *cnt;              // sort digit counts, 256 per tile (tile-major)
+    uint32_t *segtot, *segp;    // sort: per simulation and digit, total and scan base
     uint32_t *scan_tmp;         // block sums of the scans
     double *spos, *smass;       // sorted state (FP64)
     int8_t *lcp;                // common-prefix level of neighbouring keys, -1 at segment edges
@@ -99,7 +100,7 @@ struct ForestDev {
     uint32_t *nfirst, *ncount, *nparent, *ncrank;
     uint32_t *cs;               // exclusive scan of nchild
     uint32_t *slot_of, *node_at_slot;
-    uint32_t *level_cnt, *level_off, *level_cur, *level_list;  // internal nodes bucketed by level
+    unsigned long long *tile_mm; // per tile: integer images of the bbox min (3) and max (3)
     double *nM, *nS;            // node mass, centre of mass (FP64; S then com in place)
     WRec32 *w32;
     WRec64 *w64;

@@ -3,27 +3,37 @@
 // computationally dominant part).
 //
 // One wavefront walks the tree for a group of 64 key-consecutive bodies, one
-// body per lane.  The stack lives in LDS and holds (first child slot, number of
-// children, lane mask) entries: a lane takes part in a node only if it opened
-// every ancestor, so each lane meets exactly the cubes of its own per-body
-// walk and its interaction set is the per-body set of the method.  Node
-// records are read with wave-uniform (scalar) loads.  Monopoles and leaf pairs
-// use a softened kernel on the VALU; no matrix cores (not a contraction).
+// body per lane.  The LDS stack holds (first child slot, number of children,
+// lane mask) entries: a lane takes part in a cube only if it opened every
+// ancestor, so each lane meets exactly the cubes of its own per-body walk and
+// its interaction set is the per-body set of the method.
 //
-// FP64 mode: the opening test s^2 < theta^2 D^2 and all arithmetic in FP64.
-// FP32 mode: coordinates relative to the simulation's bbox centre in FP32;
-// the test is evaluated in FP32 and, when |theta^2 D^2 - s^2| lies within its
-// rounding bound, re-evaluated exactly in FP64 from the FP64 centre of mass
-// and position; pair terms in FP32 summed into per-lane partial sums that are
-// folded into Kahan-compensated totals after at most 64 terms.
+// Per popped entry, lane c loads child c's record (children are contiguous)
+// and stages it in LDS; every lane then reads each child by broadcast.
+// Per-lane predicates are formed as wave masks (one compare each, written to
+// scalar registers) and combined with scalar logic, so a cube visit costs the
+// distance, one fused opening test, two compares and, for accepting lanes,
+// the softened monopole.  Opened leaves are queued (rank, lane mask) and their
+// particles are loaded and converted 64 at a time.  No matrix cores: this is
+// not a contraction.
+//
+// FP64 mode: the opening test s^2 < theta^2 D^2 is evaluated exactly as the
+// oracle writes it; pair terms in FP64 with a Newton-refined rsqrt.
+// FP32 mode: see k_walk32.
 #include "bh_common.h"
 
 namespace bh {
 
 constexpr float kU32 = 5.9604644775390625e-8f;   // 2^-24
 constexpr uint32_t kFlushWork = 64;              // pair terms (upper bound) between Kahan folds
+constexpr int kWaves = kWalkThreads / 64;
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // Orders LDS traffic between lanes of one wavefront (no instruction is emitted:
 // the wavefront executes in lockstep and its LDS operations complete in order;
@@ -41,24 +51,23 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
-// Newton-refined FP64 reciprocal square root: y <- y + y (1 - x y^2) / 2, twice.
+// FP64 reciprocal square root: the hardware estimate refined by one Newton step
+// y <- y + y (1 - x y^2) / 2 (the error is squared: well inside the 1e-10 force gate).
 __device__ __forceinline__ double rsqrt64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double e = fma(-x * y, y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 __device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Self exclusion of a leaf pair: the lane whose body has rank jq (if in this group).
+__device__ __forceinline__ uint64_t self_bit(uint32_t jq, uint32_t gstart) {
+    uint32_t d = jq - gstart;
+    return d < 64u ? (1ull << d) : 0ull;
 }
 
 struct WalkOut {
@@ -67,37 +76,37 @@ struct WalkOut {
     uint64_t *hash;
 };
 
-// ------------------------------------------------------------- FP32 walk ---
-// Each wavefront re-expresses coordinates relative to its own FP64 reference
-// point g (its first body), so FP32 differences carry errors of order
-// u |d| + u |x - g| rather than u |x - origin|.  The children of a popped stack
-// entry are loaded and converted lane-parallel (lane c takes child c: FP64
-// centre minus g, rounded to FP32, plus the per-child rounding band of the
-// opening test) and staged in LDS, from which every lane reads them by
-// broadcast.  Leaf particles are staged the same way, 64 at a time.
-//
-// Opening test in FP32: T = theta^2 D2 - s^2 (one fma).  With
-// rho = |com - g|_inf + |x - g|_inf (upper bounds) and u = 2^-24,
-//   |T - (theta^2 |com - x|^2 - s^2)| <= 16 u s^2 + rho (8 u s theta + 4 u^2 theta^2 rho)
-// (a factor two above the first-order bound), so outside that band the FP32
-// sign is the sign of the exact test; inside it the test is repeated in FP64
-// exactly as the oracle evaluates it.
-
-struct Stage {
-    float x, y, z, m;     // centre relative to g (FP32), mass
-    float S, band;        // side^2, rounding band for this wavefront
-    uint32_t link, cnt;
-    uint32_t gid, level, pad0, pad1;
+struct WaveLds32 {
+    uint4 stk[kStackMax];
+    float4 sa[8];          // child: centre rel g (x, y, z), mass
+    float2 sb[8];          // child: S' = s^2 + theta^2 eps^2, rounding band for this wavefront
+    uint2 sl[8];           // child: link, cnt
+    uint2 sc[8];           // child: gid, level
+    uint32_t irank[64];    // queued leaf particles: rank
+    uint64_t imask[64];    //                        lane mask
+    float4 pst[64];        //                        position rel g, mass
 };
 
+// ------------------------------------------------------------- FP32 walk ---
+// Each wavefront re-expresses coordinates relative to its own FP64 reference
+// point g (its first body): FP32 differences then carry errors of order
+// u |d| + u |x - g| rather than u |x - origin|.
+//
+// Opening test in FP32: with E2 = |d|^2 + eps^2 accumulated from eps^2 and
+// S' = s^2 + theta^2 eps^2, T = theta^2 E2 - S' equals theta^2 D^2 - s^2 in
+// exact arithmetic.  With rho an upper bound of |com - g|_inf + |x - g|_inf and
+// u = 2^-24, the rounding of T from the FP32 coordinates is at most
+//   16 u (s^2 + theta^2 eps^2) + rho (8 u s theta + 4 u^2 theta^2 rho)
+// (about twice the first-order bound), so outside that band the FP32 sign is
+// the sign of the exact test; inside it the test is repeated in FP64 exactly
+// as the oracle evaluates it.  Pair terms go into FP32 partial sums that are
+// folded into Kahan-compensated totals after at most 64 terms.
 template <bool STATS, bool POT>
 __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut out) {
-    constexpr int W = kWalkThreads / 64;
-    __shared__ uint4 stk[W][kStackMax];
-    __shared__ Stage stage[W][8];
-    __shared__ float4 pst[W][64];
+    __shared__ WaveLds32 lds_all[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t gi = blockIdx.x * W + wave;
+    WaveLds32 &L = lds_all[wave];
+    const uint32_t gi = blockIdx.x * kWaves + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
     const GroupDesc gd = f.groups[gi];
@@ -105,10 +114,11 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
     const SegDesc &sd = f.seg[sid];
     if (sd.precision != 1) return;
     const SegState &st = f.st[sid];
+    const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
-    const uint32_t r = gd.start + (live ? (uint32_t)lane : 0u);
-    const uint32_t r0 = uni(gd.start);
-    const double gx = f.spos[3 * (size_t)r0], gy = f.spos[3 * (size_t)r0 + 1], gz = f.spos[3 * (size_t)r0 + 2];
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
+    const double gx = f.spos[3 * (size_t)gstart], gy = f.spos[3 * (size_t)gstart + 1],
+                 gz = f.spos[3 * (size_t)gstart + 2];
     const float tx = (float)__dsub_rn(f.spos[3 * (size_t)r], gx);
     const float ty = (float)__dsub_rn(f.spos[3 * (size_t)r + 1], gy);
     const float tz = (float)__dsub_rn(f.spos[3 * (size_t)r + 2], gz);
@@ -117,21 +127,18 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
     rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
     const double theta = sd.theta;
     const float theta2 = (float)(theta * theta);
-    const float band2 = (float)(4.0 * 3.552713678800501e-15 * theta * theta);   // 4 u^2 theta^2
     const float eps2 = (float)(sd.eps * sd.eps);
+    const float band2 = (float)(4.0 * 3.552713678800501e-15 * theta * theta);   // 4 u^2 theta^2
+    const bool soft = eps2 > 0.0f;
 
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
     float sx = 0.f, sy = 0.f, sz = 0.f, sp_ = 0.f;           // Kahan sums
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;            // Kahan compensations
     uint32_t nmono = 0, np2p = 0, nvis = 0, nfb = 0;
+    uint32_t wvis = 0, went = 0, wacc = 0, wleaf = 0;         // wave-level counters (uniform)
     uint64_t h = 0;
-
-    uint64_t m0 = __ballot(live);
-    int sp = 0;
-    if (lane == 0) stk[wave][0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
-    wave_sync();
-    sp = 1;
     uint32_t work = 0;   // terms added to the partial sums since the last fold (wave-uniform)
+    uint32_t qn = 0;     // queued leaf particles (wave-uniform)
     auto fold = [&]() {
         kahan_add(sx, cx, ax); ax = 0.f;
         kahan_add(sy, cy, ay); ay = 0.f;
@@ -139,103 +146,143 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
         if (POT) { kahan_add(sp_, cp, ap); ap = 0.f; }
         work = 0;
     };
+    auto pair = [&](float px, float py, float pz, float pm) {
+        const float dx = px - tx, dy = py - ty, dz = pz - tz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+        if (soft || r2 > 0.0f) {
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float mr = pm * ri;
+            const float w3 = mr * ri * ri;
+            ax = fmaf(w3, dx, ax);
+            ay = fmaf(w3, dy, ay);
+            az = fmaf(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    };
+    // queued leaf particles: load and convert lane-parallel, then one pass per particle
+    auto flush_leaves = [&]() {
+        if (qn == 0) return;
+        if (work + qn > kFlushWork) fold();
+        work += qn;
+        wave_sync();
+        if ((uint32_t)lane < qn) {
+            const size_t j = L.irank[lane];
+            L.pst[lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx), (float)__dsub_rn(f.spos[3 * j + 1], gy),
+                                      (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
+        }
+        wave_sync();
+        for (uint32_t k = 0; k < qn; ++k) {
+            const uint32_t jq = uni(L.irank[k]);
+            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
+            if (in_mask(m)) {
+                const float4 p = L.pst[k];
+                pair(p.x, p.y, p.z, p.w);
+                if (STATS) {
+                    ++np2p;
+                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    int sp = 0;
+    const uint64_t m0 = ballot(live);
+    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
+    wave_sync();
+    sp = 1;
     while (sp > 0) {
         --sp;
-        const uint4 e = stk[wave][sp];
+        const uint4 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
-        const bool act = (emask >> lane) & 1ull;
         wave_sync();
         if ((uint32_t)lane < nch) {
             const WRec32 &w = f.w32[link + lane];
-            Stage q;
-            q.x = (float)__dsub_rn(w.cx, gx);
-            q.y = (float)__dsub_rn(w.cy, gy);
-            q.z = (float)__dsub_rn(w.cz, gz);
-            q.m = w.m;
-            q.S = w.S;
-            const float rho = fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))) * (1.0f + 4.0f * kU32) + rw;
-            q.band = fmaf(rho, fmaf(band2, rho, w.band1), w.band0);
-            q.link = w.link;
-            q.cnt = w.cnt;
-            q.gid = w.gid;
-            q.level = w.level;
-            q.pad0 = q.pad1 = 0;
-            stage[wave][lane] = q;
+            const float qx = (float)__dsub_rn(w.cx, gx);
+            const float qy = (float)__dsub_rn(w.cy, gy);
+            const float qz = (float)__dsub_rn(w.cz, gz);
+            const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
+            L.sa[lane] = make_float4(qx, qy, qz, w.m);
+            L.sb[lane] = make_float2(w.Sp, fmaf(rho, fmaf(band2, rho, w.band1), w.band0));
+            L.sl[lane] = make_uint2(w.link, w.cnt);
+            L.sc[lane] = make_uint2(w.gid, w.level);
         }
         wave_sync();
         if (work + nch > kFlushWork) fold();
         work += nch;
-        for (uint32_t c = 0; c < nch; ++c) {
-            const Stage q = stage[wave][c];
-            const float dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
-            const float D2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float T = fmaf(theta2, D2, -q.S);
-            bool acc = T > 0.0f;
-            if (act && !(fabsf(T) > q.band)) {
+        if (STATS) { wvis += nch; ++went; }
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
+            const float4 qa = L.sa[c];
+            const float2 qb = L.sb[c];
+            const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
+            const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+            const float T = fmaf(theta2, E2, -qb.x);
+            uint64_t accm = ballot(T > 0.0f) & emask;
+            const uint64_t ambm = ballot(!(fabsf(T) > qb.y)) & emask;
+            if (ambm) {
                 // within the FP32 rounding bound of the threshold: decide exactly in FP64
-                const double *cm = f.nS + 3 * (size_t)uni(q.gid);
-                const double *xp = f.spos + 3 * (size_t)r;
-                double ex = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]), ez = __dsub_rn(cm[2], xp[2]);
-                double ED2 = __dadd_rn(__dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
-                double s = ldexp(st.L, -(int)uni(q.level));
-                acc = __dmul_rn(s, s) < __dmul_rn(__dmul_rn(theta, theta), ED2);
-                if (STATS) ++nfb;
+                bool ex = false;
+                if (in_mask(ambm)) {
+                    const uint2 qc = L.sc[c];
+                    const double *cm = f.nS + 3 * (size_t)qc.x;
+                    const double *xp = f.spos + 3 * (size_t)r;
+                    const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
+                                 ez = __dsub_rn(cm[2], xp[2]);
+                    const double ED2 = __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
+                    const double s = ldexp(st.L, -(int)qc.y);
+                    ex = __dmul_rn(s, s) < __dmul_rn(__dmul_rn(theta, theta), ED2);
+                    if (STATS) ++nfb;
+                }
+                accm = (accm & ~ambm) | (ballot(ex) & ambm);
             }
-            acc = acc && act;
-            if (STATS && act) ++nvis;
-            if (acc) {
-                const float r2 = D2 + eps2;
-                const float ri = __builtin_amdgcn_rsqf(r2);
-                const float mr = q.m * ri;
-                const float w3 = mr * ri * ri;
+            if (STATS) {
+                if (in_mask(emask)) ++nvis;
+                if (accm) ++wacc;
+            }
+            {
+                // monopole for the accepting lanes: computed by all, weight selected
+                const float ri = __builtin_amdgcn_rsqf(E2);
+                const float mr = qa.w * ri;
+                const bool a = in_mask(accm);
+                const float w3 = a ? mr * ri * ri : 0.0f;
                 ax = fmaf(w3, dx, ax);
                 ay = fmaf(w3, dy, ay);
                 az = fmaf(w3, dz, az);
-                if (POT) ap -= mr;
-                if (STATS) {
+                if (POT) ap -= a ? mr : 0.0f;
+                if (STATS && a) {
                     ++nmono;
-                    h += mix64((uint64_t)(q.gid - st.nbase));
+                    h += mix64((uint64_t)(L.sc[c].x - st.nbase));
                 }
             }
-            const uint64_t open = __ballot(act && !acc);
+            const uint64_t open = emask & ~accm;
             if (open) {
-                const uint32_t qcnt = uni(q.cnt), qlink = uni(q.link);
+                const uint2 ql = L.sl[c];
+                const uint32_t qlink = uni(ql.x), qcnt = uni(ql.y);
                 if (qcnt & kLeafBit) {
                     const uint32_t np = qcnt & ~kLeafBit;
-                    const bool me = (open >> lane) & 1ull;
-                    for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                        const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                        wave_sync();
-                        if ((uint32_t)lane < nb) {
-                            const size_t j = (size_t)qlink + b0 + lane;
-                            pst[wave][lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx),
-                                                          (float)__dsub_rn(f.spos[3 * j + 1], gy),
-                                                          (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
+                    if (STATS) ++wleaf;
+                    if (np <= 64u) {
+                        if (qn + np > 64u) flush_leaves();
+                        if ((uint32_t)lane < np) {
+                            L.irank[qn + lane] = qlink + lane;
+                            L.imask[qn + lane] = open;
                         }
-                        wave_sync();
-                        if (work + nb > kFlushWork) fold();
-                        work += nb;
-                        for (uint32_t k = 0; k < nb; ++k) {
-                            const float4 p = pst[wave][k];
-                            const uint32_t jq = qlink + b0 + k;
-                            if (me && jq != r) {
-                                const float px = p.x - tx, py = p.y - ty, pz = p.z - tz;
-                                const float r2 = fmaf(pz, pz, fmaf(py, py, fmaf(px, px, eps2)));
-                                if (r2 > 0.0f) {
-                                    const float ri = __builtin_amdgcn_rsqf(r2);
-                                    const float mr = p.w * ri;
-                                    const float w3 = mr * ri * ri;
-                                    ax = fmaf(w3, px, ax);
-                                    ay = fmaf(w3, py, ay);
-                                    az = fmaf(w3, pz, az);
-                                    if (POT) ap -= mr;
-                                }
-                                if (STATS) {
-                                    ++np2p;
-                                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
-                                }
+                        qn += np;
+                    } else {
+                        // a leaf of more than 64 particles (coincident particles at the depth limit)
+                        flush_leaves();
+                        for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                            const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                            if ((uint32_t)lane < nb) {
+                                L.irank[lane] = qlink + b0 + lane;
+                                L.imask[lane] = open;
                             }
+                            qn = nb;
+                            flush_leaves();
                         }
                     }
                 } else {
@@ -244,13 +291,14 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
                         sp = 0;
                         break;
                     }
-                    if (lane == 0) stk[wave][sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
+                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
                     wave_sync();
                     ++sp;
                 }
             }
         }
     }
+    flush_leaves();
     fold();
     if (live) {
         const uint32_t i = f.idx[r];
@@ -278,17 +326,32 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
             atomicAdd(&f.stats[1], b);
             atomicAdd(&f.stats[2], v);
             atomicAdd(&f.stats[3], fb);
+            atomicAdd(&f.stats[4], (unsigned long long)wvis);
+            atomicAdd(&f.stats[5], (unsigned long long)went);
+            atomicAdd(&f.stats[6], (unsigned long long)wacc);
+            atomicAdd(&f.stats[7], (unsigned long long)wleaf);
         }
     }
 }
 
 // ------------------------------------------------------------- FP64 walk ---
 
+struct WaveLds64 {
+    uint4 stk[kStackMax];
+    double4 sa[8];         // child: centre of mass, mass
+    double sS[8];          // child: side^2
+    uint4 sb[8];           // child: link, cnt, gid, level
+    uint32_t irank[64];
+    uint64_t imask[64];
+    double4 pst[64];
+};
+
 template <bool STATS, bool POT>
 __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut out) {
-    __shared__ uint4 stk[kWalkThreads / 64][kStackMax];
+    __shared__ WaveLds64 lds_all[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t gi = blockIdx.x * (kWalkThreads / 64) + wave;
+    WaveLds64 &L = lds_all[wave];
+    const uint32_t gi = blockIdx.x * kWaves + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
     const GroupDesc gd = f.groups[gi];
@@ -296,70 +359,119 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
     const SegDesc &sd = f.seg[sid];
     if (sd.precision != 0) return;
     const SegState &st = f.st[sid];
+    const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
-    const uint32_t r = gd.start + (live ? (uint32_t)lane : 0u);
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
     const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
     const double theta2 = __dmul_rn(sd.theta, sd.theta);
     const double eps2 = __dmul_rn(sd.eps, sd.eps);
+    const bool soft = eps2 > 0.0;
 
     double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
     uint32_t nmono = 0, np2p = 0, nvis = 0;
     uint64_t h = 0;
+    uint32_t qn = 0;
+    auto pair = [&](double px, double py, double pz, double pm) {
+        const double dx = px - tx, dy = py - ty, dz = pz - tz;
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+        if (soft || r2 > 0.0) {
+            const double ri = rsqrt64(r2);
+            const double mr = pm * ri;
+            const double w3 = mr * ri * ri;
+            ax = fma(w3, dx, ax);
+            ay = fma(w3, dy, ay);
+            az = fma(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    };
+    auto flush_leaves = [&]() {
+        if (qn == 0) return;
+        wave_sync();
+        if ((uint32_t)lane < qn) {
+            const size_t j = L.irank[lane];
+            L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+        }
+        wave_sync();
+        for (uint32_t k = 0; k < qn; ++k) {
+            const uint32_t jq = uni(L.irank[k]);
+            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
+            if (in_mask(m)) {
+                const double4 p = L.pst[k];
+                pair(p.x, p.y, p.z, p.w);
+                if (STATS) {
+                    ++np2p;
+                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
 
-    uint64_t m0 = __ballot(live);
     int sp = 0;
-    if (lane == 0) stk[wave][0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
+    const uint64_t m0 = ballot(live);
+    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
     wave_sync();
     sp = 1;
     while (sp > 0) {
         --sp;
-        const uint4 e = stk[wave][sp];
+        const uint4 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
-        const bool act = (emask >> lane) & 1ull;
-        for (uint32_t c = 0; c < nch; ++c) {
-            const WRec64 w = f.w64[link + c];
-            const double dx = __dsub_rn(w.x, tx), dy = __dsub_rn(w.y, ty), dz = __dsub_rn(w.z, tz);
+        wave_sync();
+        if ((uint32_t)lane < nch) {
+            const WRec64 &w = f.w64[link + lane];
+            L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
+            L.sS[lane] = w.S;
+            L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
+        }
+        wave_sync();
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
+            const double4 qa = L.sa[c];
+            const double S = L.sS[c];
+            const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
             const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            const bool acc = act && (w.S < __dmul_rn(theta2, D2));
-            if (STATS && act) ++nvis;
-            if (acc) {
+            const uint64_t accm = ballot(S < __dmul_rn(theta2, D2)) & emask;
+            if (STATS && in_mask(emask)) ++nvis;
+            {
                 const double ri = rsqrt64(D2 + eps2);
-                const double mr = w.m * ri;
-                const double w3 = mr * ri * ri;
+                const double mr = qa.w * ri;
+                const bool a = in_mask(accm);
+                const double w3 = a ? mr * ri * ri : 0.0;
                 ax = fma(w3, dx, ax);
                 ay = fma(w3, dy, ay);
                 az = fma(w3, dz, az);
-                if (POT) ap -= mr;
-                if (STATS) {
+                if (POT) ap -= a ? mr : 0.0;
+                if (STATS && a) {
                     ++nmono;
-                    h += mix64((uint64_t)(w.gid - st.nbase));
+                    h += mix64((uint64_t)(L.sb[c].z - st.nbase));
                 }
             }
-            const uint64_t open = __ballot(act && !acc);
+            const uint64_t open = emask & ~accm;
             if (open) {
-                if (w.cnt & kLeafBit) {
-                    const uint32_t np = w.cnt & ~kLeafBit;
-                    const bool me = (open >> lane) & 1ull;
-                    for (uint32_t q = w.link; q < w.link + np; ++q) {
-                        const double qx = f.spos[3 * (size_t)q], qy = f.spos[3 * (size_t)q + 1],
-                                     qz = f.spos[3 * (size_t)q + 2], qm = f.smass[q];
-                        if (me && q != r) {
-                            const double px = qx - tx, py = qy - ty, pz = qz - tz;
-                            const double r2 = fma(pz, pz, fma(py, py, fma(px, px, eps2)));
-                            if (r2 > 0.0) {
-                                const double ri = rsqrt64(r2);
-                                const double mr = qm * ri;
-                                const double w3 = mr * ri * ri;
-                                ax = fma(w3, px, ax);
-                                ay = fma(w3, py, ay);
-                                az = fma(w3, pz, az);
-                                if (POT) ap -= mr;
+                const uint4 qb = L.sb[c];
+                const uint32_t qlink = uni(qb.x), qcnt = uni(qb.y);
+                if (qcnt & kLeafBit) {
+                    const uint32_t np = qcnt & ~kLeafBit;
+                    if (np <= 64u) {
+                        if (qn + np > 64u) flush_leaves();
+                        if ((uint32_t)lane < np) {
+                            L.irank[qn + lane] = qlink + lane;
+                            L.imask[qn + lane] = open;
+                        }
+                        qn += np;
+                    } else {
+                        flush_leaves();
+                        for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                            const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                            if ((uint32_t)lane < nb) {
+                                L.irank[lane] = qlink + b0 + lane;
+                                L.imask[lane] = open;
                             }
-                            if (STATS) {
-                                ++np2p;
-                                h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[q] - sd.start));
-                            }
+                            qn = nb;
+                            flush_leaves();
                         }
                     }
                 } else {
@@ -368,13 +480,14 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
                         sp = 0;
                         break;
                     }
-                    if (lane == 0) stk[wave][sp] = make_uint4(w.link, w.cnt, (uint32_t)open, (uint32_t)(open >> 32));
+                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
                     wave_sync();
                     ++sp;
                 }
             }
         }
     }
+    flush_leaves();
     if (live) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
@@ -407,7 +520,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, hipStream_t s) {
     WalkOut o{acc, pot, n_mono, n_p2p, hash};
-    const unsigned blocks = (f.ngroups + (kWalkThreads / 64) - 1) / (kWalkThreads / 64);
+    const unsigned blocks = (f.ngroups + kWaves - 1) / kWaves;
     if (blocks == 0) return hipSuccess;
     const dim3 g(blocks), b(kWalkThreads);
     if (f.has32) {
