@@ -1,0 +1,149 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark uses, on outputs the oracle computes one by one (sampled targets):
+the 2^20 Plummer sphere, the 2^22 two-sphere and uniform-cube systems over the
+theta sweep, the 512-simulation batch, and a served request."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.gpu_helpers import dev, rel_max, rel_rms, u64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bh = pytest.importorskip("paper_1109_5190_amd")
+
+CORES = len(os.sched_getaffinity(0))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = bh.Context(0)
+    yield c
+    c.sync()
+
+
+def sampled_check(T, gpu, targets, theta, eps, prec):
+    ref = T.walk(theta, eps, 1.0, targets, nthreads=CORES)
+    idx = torch.tensor(targets, device="cuda")
+    assert np.array_equal(gpu["n_mono"][idx].cpu().numpy(), ref["n_mono"])
+    assert np.array_equal(gpu["n_p2p"][idx].cpu().numpy(), ref["n_p2p"])
+    assert np.array_equal(u64(gpu["hash"][idx]), ref["hash"])
+    acc = gpu["acc"][idx].cpu().numpy()
+    if prec == "fp64":
+        assert rel_rms(acc, ref["acc"]) <= 1e-10
+    else:
+        assert rel_rms(acc, ref["acc"]) <= 2e-6
+        assert rel_max(acc, ref["acc"]) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def plummer_1m():
+    s = icgen.plummer(1 << 20, 2)
+    return s, oracle.Tree(s.pos, s.mass, 1)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_plummer_1m_sampled(ctx, plummer_1m, prec):
+    """Headline workload: N = 2^20, eps = 0.005, theta = 0.5, leaf_cap 1."""
+    s, T = plummer_1m
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.5, 0.005, precision=prec)).upward()
+    r = t.forces_stats()
+    # the benchmark times the walk without counters: it must give the same bits
+    assert torch.equal(t.forces(), r["acc"])
+    nn, lo, k = t.info()
+    assert nn == T.nn and k == T.k
+    rng = np.random.default_rng(11)
+    targets = np.sort(rng.choice(s.n, 4096, replace=False)).astype(np.int64)
+    sampled_check(T, r, targets, 0.5, 0.005, prec)
+
+
+def big_systems():
+    return {"two_spheres": icgen.two_plummer(1 << 21, 3, 4), "cube": icgen.uniform_cube(1 << 22, 5)}
+
+
+@pytest.fixture(scope="module")
+def systems_4m():
+    out = {}
+    for name, s in big_systems().items():
+        out[name] = (s, oracle.Tree(s.pos, s.mass, 1))
+    return out
+
+
+@pytest.mark.parametrize("name", ["two_spheres", "cube"])
+def test_theta_sweep_4m_sampled(ctx, systems_4m, name):
+    """Two unit-mass Plummer spheres of 2^21 at +-5 and a uniform cube of 2^22, eps = 0.005,
+    theta in {0.3, 0.5, 0.7, 1.0}, FP32 and FP64, 1024 sampled targets each."""
+    s, T = systems_4m[name]
+    pos, mass = dev(s.pos), dev(s.mass)
+    rng = np.random.default_rng(12)
+    targets = np.sort(rng.choice(s.n, 1024, replace=False)).astype(np.int64)
+    for theta in (0.3, 0.5, 0.7, 1.0):
+        for prec in ("fp32", "fp64"):
+            print(f"[sweep] {name} theta={theta} {prec}", flush=True)
+            t = bh.Tree(ctx, pos, mass, bh.params(theta, 0.005, precision=prec)).upward()
+            r = t.forces_stats()
+            sampled_check(T, r, targets, theta, 0.005, prec)
+            del t, r
+
+
+def test_batch_512_forest_sampled(ctx):
+    """512 Plummer instances, N log-uniform in [1024, 262144], theta from {0.4, 0.5, 0.7}, eps = 0.01,
+    FP32, one forest; 16 instances stratified by N checked against the oracle, plus two KDK steps
+    recorded as a graph against the oracle's own trajectory for the 4 smallest of them."""
+    inst = icgen.batch_instances(512, 6)
+    systems = [icgen.plummer(n, seed) for n, _, seed in inst]
+    cat = icgen.concat(*systems)
+    ns = [n for n, _, _ in inst]
+    plist = [bh.params(th, 0.01, precision="fp32") for _, th, _ in inst]
+    forest = bh.Forest(ctx, ns, plist, dev(cat.pos), dev(cat.vel), dev(cat.mass))
+    acc = forest.forces().cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    order = np.argsort(ns)
+    pick = order[np.linspace(0, len(ns) - 1, 16).astype(int)]
+    rng = np.random.default_rng(13)
+    for k in pick:
+        s = systems[k]
+        tg = np.sort(rng.choice(s.n, min(s.n, 512), replace=False)).astype(np.int64)
+        ref = oracle.forces(s.pos, s.mass, theta=inst[k][1], eps=0.01, targets=tg, nthreads=CORES)
+        a = acc[offs[k]:offs[k + 1]][tg]
+        assert rel_rms(a, ref["acc"]) <= 2e-6, k
+        assert rel_max(a, ref["acc"]) <= 1e-4, k
+    forest.step_graph(2, [1e-3] * len(ns))
+    pos = forest.pos.cpu().numpy()
+    acc = forest.acc.cpu().numpy()
+    for k in pick[:4]:
+        s = systems[k]
+        x, v, a, _ = oracle.kdk(s.pos, s.vel, s.mass, 1e-3, 2, theta=inst[k][1], eps=0.01, nthreads=CORES)
+        # FP32 forces (<= 1e-4 relative, |a| <~ 10 here) move positions by <~ dt^2 * 1e-3 per step
+        assert np.abs(pos[offs[k]:offs[k + 1]] - x).max() <= 1e-7
+        assert rel_rms(acc[offs[k]:offs[k + 1]], a) <= 2e-6
+
+
+def test_served_request_matches_oracle(ctx):
+    """A request served next to others (device initial conditions) against the oracle's KDK
+    from the host generator's initial conditions (the two generators agree to 1e-12)."""
+    sv = bh.Server(ctx, 2 << 30, max_slots=8, max_resident=1 << 20)
+    p = bh.params(0.5, 0.01, precision="fp64")
+    rid = sv.submit(8192, 3, 0, 4242, p, 1e-3)
+    others = [sv.submit(20000 + 1000 * k, 4, k % 2, 100 + k, bh.params(0.7, 0.01, precision="fp32"), 1e-3,
+                        release=True) for k in range(4)]
+    t0 = time.time()
+    while sv.poll(rid)["state"] not in ("done", "failed"):
+        assert time.time() - t0 < 60
+        time.sleep(0.002)
+    for o in others:
+        while sv.poll(o)["state"] not in ("done", "failed"):
+            time.sleep(0.002)
+    pos, vel = sv.fetch(rid, 8192)
+    sv.close()
+    s = icgen.plummer(8192, 4242)
+    x, v, a, _ = oracle.kdk(s.pos, s.vel, s.mass, 1e-3, 3, theta=0.5, eps=0.01)
+    assert np.abs(pos.cpu().numpy() - x).max() <= 1e-10
+    assert np.abs(vel.cpu().numpy() - v).max() <= 1e-9
