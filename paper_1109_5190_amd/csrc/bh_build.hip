@@ -733,19 +733,28 @@ __global__ void k_records(ForestDev f) {
         w.cy = c[1];
         w.cz = c[2];
         w.m = (float)M;
-        // FP32 opening test constants (see the walk): exact side^2 when in FP32 range, else always FP64
-        const int e2 = 2 * (st.k - level);
+        // FP32 opening test: accept iff |d|^2 + eps^2 > side^2 / theta^2 + eps^2 (the walk adds
+        // its rounding band); S is kept only when it and eps^2 are well inside the FP32 range,
+        // otherwise every test of this node is decided in FP64.
         const double u = 5.9604644775390625e-8;   // 2^-24
-        const float theta2f = (float)(sd.theta * sd.theta), eps2f = (float)(sd.eps * sd.eps);
-        if (e2 > -120 && e2 < 120) {
-            const float S = ldexpf(1.0f, e2);
-            w.Sp = fmaf(theta2f, eps2f, S);
-            w.band0 = (float)(16.0 * u * ((double)S + (double)theta2f * (double)eps2f));
-            w.band1 = (float)(8.0 * u * s * sd.theta * (1.0 + 1e-6));
-        } else {
-            w.Sp = 0.0f;
-            w.band0 = INFINITY;
+        const double eps2 = sd.eps * sd.eps;
+        const float eps2f = (float)eps2;
+        const bool eps_ok = eps2 == 0.0 || (eps2 > 1e-30 && eps2 < 1e30 && eps2f > 0.0f);
+        if (sd.theta == 0.0) {
+            w.Sp = INFINITY;   // nothing is ever accepted
+            w.band0 = 0.0f;
             w.band1 = 0.0f;
+        } else {
+            const double S = s * s / (sd.theta * sd.theta) + eps2;
+            if (eps_ok && s * s > 1e-30 && S > 1e-30 && S < 1e30) {
+                w.Sp = (float)S;
+                w.band0 = (float)(16.0 * u * S * (1.0 + 1e-6));
+                w.band1 = (float)(8.0 * u * s / sd.theta * (1.0 + 1e-6));
+            } else {
+                w.Sp = 0.0f;
+                w.band0 = INFINITY;
+                w.band1 = 0.0f;
+            }
         }
         w.link = link;
         w.cnt = cnt;

@@ -59,9 +59,9 @@ struct GroupDesc { uint32_t start, count, seg, pad; };
 struct WRec32 {
     double cx, cy, cz;         // centre of mass (FP64)
     float m;                   // mass (FP32)
-    float Sp;                  // S' = side^2 + theta^2 eps^2 (FP32)
-    float band0;               // 16 u S' (inf: side^2 outside FP32 range, always decide in FP64)
-    float band1;               // 8 u side theta
+    float Sp;                  // S = side^2 / theta^2 + eps^2 (FP32; +inf when theta = 0)
+    float band0;               // 16 u S (inf: S outside FP32 range, always decide in FP64)
+    float band1;               // 8 u side / theta
     uint32_t link;             // internal: first child slot; leaf: first particle rank
     uint32_t cnt;              // internal: children; leaf: particles | kLeafBit
     uint32_t gid;              // global node id (depth-first preorder)

@@ -79,7 +79,7 @@ struct WalkOut {
 struct WaveLds32 {
     uint4 stk[kStackMax];
     float4 sa[8];          // child: centre rel g (x, y, z), mass
-    float2 sb[8];          // child: S' = s^2 + theta^2 eps^2, rounding band for this wavefront
+    float2 sb[8];          // child: accept above hi, decide in FP64 at or above lo (this wavefront)
     uint2 sl[8];           // child: link, cnt
     uint2 sc[8];           // child: gid, level
     uint32_t irank[64];    // queued leaf particles: rank
@@ -92,15 +92,19 @@ struct WaveLds32 {
 // point g (its first body): FP32 differences then carry errors of order
 // u |d| + u |x - g| rather than u |x - origin|.
 //
-// Opening test in FP32: with E2 = |d|^2 + eps^2 accumulated from eps^2 and
-// S' = s^2 + theta^2 eps^2, T = theta^2 E2 - S' equals theta^2 D^2 - s^2 in
-// exact arithmetic.  With rho an upper bound of |com - g|_inf + |x - g|_inf and
-// u = 2^-24, the rounding of T from the FP32 coordinates is at most
-//   16 u (s^2 + theta^2 eps^2) + rho (8 u s theta + 4 u^2 theta^2 rho)
-// (about twice the first-order bound), so outside that band the FP32 sign is
-// the sign of the exact test; inside it the test is repeated in FP64 exactly
-// as the oracle evaluates it.  Pair terms go into FP32 partial sums that are
-// folded into Kahan-compensated totals after at most 64 terms.
+// Opening test in FP32: for theta > 0 the method accepts iff s^2 < theta^2 D^2,
+// i.e. iff E2 = |d|^2 + eps^2 exceeds S = s^2 / theta^2 + eps^2 (E2 is the
+// softened distance the monopole needs anyway, so the test costs one compare).
+// With rho an upper bound of |com - g|_inf + |x - g|_inf and u = 2^-24, the
+// computed E2 - S differs from the exact D^2 - s^2 / theta^2 by less than
+//   B = 16 u S + rho (8 u s / theta + 16 u^2 rho)
+// wherever the two could differ in sign (first-order terms about half of
+// these, the rho^2 term covers the case of a target within FP32 resolution of
+// a small cube).  Per child and wavefront the walk stages hi >= S + B and
+// lo <= S - B: E2 > hi accepts, E2 < lo opens, and the rare lanes in between
+// repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
+// into FP32 partial sums that are folded into Kahan-compensated totals after
+// at most 64 terms.
 template <bool STATS, bool POT>
 __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut out) {
     __shared__ WaveLds32 lds_all[kWaves];
@@ -126,9 +130,8 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
     for (int o = 32; o > 0; o >>= 1) rw = fmaxf(rw, __shfl_xor(rw, o, 64));
     rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
     const double theta = sd.theta;
-    const float theta2 = (float)(theta * theta);
     const float eps2 = (float)(sd.eps * sd.eps);
-    const float band2 = (float)(4.0 * 3.552713678800501e-15 * theta * theta);   // 4 u^2 theta^2
+    const float band2 = 16.0f * kU32 * kU32;   // 16 u^2
     const bool soft = eps2 > 0.0f;
 
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
@@ -204,8 +207,9 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
             const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
+            const float B = fmaf(rho, fmaf(band2, rho, w.band1), w.band0);
             L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            L.sb[lane] = make_float2(w.Sp, fmaf(rho, fmaf(band2, rho, w.band1), w.band0));
+            L.sb[lane] = make_float2((w.Sp + B) * (1.0f + 4.0f * kU32), fmaxf(w.Sp - B, 0.0f) * (1.0f - 4.0f * kU32));
             L.sl[lane] = make_uint2(w.link, w.cnt);
             L.sc[lane] = make_uint2(w.gid, w.level);
         }
@@ -217,83 +221,82 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut ou
         for (uint32_t c = 0; c < 8; ++c) {
             if (c >= nch) break;
             const float4 qa = L.sa[c];
-            const float2 qb = L.sb[c];
             const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
             const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-            const float T = fmaf(theta2, E2, -qb.x);
-            uint64_t accm = ballot(T > 0.0f) & emask;
-            const uint64_t ambm = ballot(!(fabsf(T) > qb.y)) & emask;
-            if (ambm) {
-                // within the FP32 rounding bound of the threshold: decide exactly in FP64
-                bool ex = false;
-                if (in_mask(ambm)) {
-                    const uint2 qc = L.sc[c];
-                    const double *cm = f.nS + 3 * (size_t)qc.x;
-                    const double *xp = f.spos + 3 * (size_t)r;
-                    const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
-                                 ez = __dsub_rn(cm[2], xp[2]);
-                    const double ED2 = __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
-                    const double s = ldexp(st.L, -(int)qc.y);
-                    ex = __dmul_rn(s, s) < __dmul_rn(__dmul_rn(theta, theta), ED2);
-                    if (STATS) ++nfb;
+            uint64_t accm = ballot(E2 > L.sb[c].x) & emask;
+            uint64_t open = emask & ~accm;
+            if (open) {
+                const uint64_t ambm = ballot(!(E2 < L.sb[c].y)) & open;
+                if (ambm) {
+                    // within the FP32 rounding bound of the threshold: decide exactly in FP64
+                    bool ex = false;
+                    if (in_mask(ambm)) {
+                        const uint2 qc = L.sc[c];
+                        const double *cm = f.nS + 3 * (size_t)qc.x;
+                        const double *xp = f.spos + 3 * (size_t)r;
+                        const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
+                                     ez = __dsub_rn(cm[2], xp[2]);
+                        const double ED2 =
+                            __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
+                        const double s = ldexp(st.L, -(int)qc.y);
+                        ex = __dmul_rn(s, s) < __dmul_rn(__dmul_rn(theta, theta), ED2);
+                        if (STATS) ++nfb;
+                    }
+                    accm |= ballot(ex) & ambm;
+                    open = emask & ~accm;
                 }
-                accm = (accm & ~ambm) | (ballot(ex) & ambm);
+                if (open) {
+                    const uint2 ql = L.sl[c];
+                    const uint32_t qlink = uni(ql.x), qcnt = uni(ql.y);
+                    if (qcnt & kLeafBit) {
+                        const uint32_t np = qcnt & ~kLeafBit;
+                        if (STATS) ++wleaf;
+                        if (np <= 64u) {
+                            if (qn + np > 64u) flush_leaves();
+                            if ((uint32_t)lane < np) {
+                                L.irank[qn + lane] = qlink + lane;
+                                L.imask[qn + lane] = open;
+                            }
+                            qn += np;
+                        } else {
+                            // a leaf of more than 64 particles (coincident particles at the depth limit)
+                            flush_leaves();
+                            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                                if ((uint32_t)lane < nb) {
+                                    L.irank[lane] = qlink + b0 + lane;
+                                    L.imask[lane] = open;
+                                }
+                                qn = nb;
+                                flush_leaves();
+                            }
+                        }
+                    } else if (sp < kStackMax) {
+                        if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
+                        wave_sync();
+                        ++sp;
+                    } else if (lane == 0) {
+                        atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                    }
+                }
             }
             if (STATS) {
                 if (in_mask(emask)) ++nvis;
                 if (accm) ++wacc;
             }
-            {
-                // monopole for the accepting lanes: computed by all, weight selected
+            if (in_mask(accm)) {
+                // softened monopole, executed by the accepting lanes only
+                __asm__ volatile("");
                 const float ri = __builtin_amdgcn_rsqf(E2);
                 const float mr = qa.w * ri;
-                const bool a = in_mask(accm);
-                const float w3 = a ? mr * ri * ri : 0.0f;
+                const float w3 = mr * ri * ri;
                 ax = fmaf(w3, dx, ax);
                 ay = fmaf(w3, dy, ay);
                 az = fmaf(w3, dz, az);
-                if (POT) ap -= a ? mr : 0.0f;
-                if (STATS && a) {
+                if (POT) ap -= mr;
+                if (STATS) {
                     ++nmono;
                     h += mix64((uint64_t)(L.sc[c].x - st.nbase));
-                }
-            }
-            const uint64_t open = emask & ~accm;
-            if (open) {
-                const uint2 ql = L.sl[c];
-                const uint32_t qlink = uni(ql.x), qcnt = uni(ql.y);
-                if (qcnt & kLeafBit) {
-                    const uint32_t np = qcnt & ~kLeafBit;
-                    if (STATS) ++wleaf;
-                    if (np <= 64u) {
-                        if (qn + np > 64u) flush_leaves();
-                        if ((uint32_t)lane < np) {
-                            L.irank[qn + lane] = qlink + lane;
-                            L.imask[qn + lane] = open;
-                        }
-                        qn += np;
-                    } else {
-                        // a leaf of more than 64 particles (coincident particles at the depth limit)
-                        flush_leaves();
-                        for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                            const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                            if ((uint32_t)lane < nb) {
-                                L.irank[lane] = qlink + b0 + lane;
-                                L.imask[lane] = open;
-                            }
-                            qn = nb;
-                            flush_leaves();
-                        }
-                    }
-                } else {
-                    if (sp >= kStackMax) {
-                        if (lane == 0) atomicOr(f.err, kErrStack);
-                        sp = 0;
-                        break;
-                    }
-                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
-                    wave_sync();
-                    ++sp;
                 }
             }
         }
@@ -435,20 +438,6 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
             const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
             const uint64_t accm = ballot(S < __dmul_rn(theta2, D2)) & emask;
             if (STATS && in_mask(emask)) ++nvis;
-            {
-                const double ri = rsqrt64(D2 + eps2);
-                const double mr = qa.w * ri;
-                const bool a = in_mask(accm);
-                const double w3 = a ? mr * ri * ri : 0.0;
-                ax = fma(w3, dx, ax);
-                ay = fma(w3, dy, ay);
-                az = fma(w3, dz, az);
-                if (POT) ap -= a ? mr : 0.0;
-                if (STATS && a) {
-                    ++nmono;
-                    h += mix64((uint64_t)(L.sb[c].z - st.nbase));
-                }
-            }
             const uint64_t open = emask & ~accm;
             if (open) {
                 const uint4 qb = L.sb[c];
@@ -474,15 +463,27 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
                             flush_leaves();
                         }
                     }
-                } else {
-                    if (sp >= kStackMax) {
-                        if (lane == 0) atomicOr(f.err, kErrStack);
-                        sp = 0;
-                        break;
-                    }
+                } else if (sp < kStackMax) {
                     if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
                     wave_sync();
                     ++sp;
+                } else if (lane == 0) {
+                    atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                }
+            }
+            if (in_mask(accm)) {
+                // softened monopole, executed by the accepting lanes only
+                __asm__ volatile("");
+                const double ri = rsqrt64(D2 + eps2);
+                const double mr = qa.w * ri;
+                const double w3 = mr * ri * ri;
+                ax = fma(w3, dx, ax);
+                ay = fma(w3, dy, ay);
+                az = fma(w3, dz, az);
+                if (POT) ap -= mr;
+                if (STATS) {
+                    ++nmono;
+                    h += mix64((uint64_t)(L.sb[c].z - st.nbase));
                 }
             }
         }
