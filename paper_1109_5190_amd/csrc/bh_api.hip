@@ -146,7 +146,11 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.ncrank = c.take<uint32_t>(Mc);
     D.cs = c.take<uint32_t>(Mc + 1);
     D.slot_of = c.take<uint32_t>(Mc);
-    D.node_at_slot = c.take<uint32_t>(Mc);
+    D.lvl_list = c.take<uint4>(256 * ((Mc + 255) / 256));
+    D.blk_lvl = c.take<uint16_t>((kMaxLevel + 2) * ((Mc + 255) / 256));
+    D.uM = c.take<double>(Mc);
+    D.uS = c.take<double>(3 * Mc);
+    D.rlam = c.take<uint8_t>(N);
     D.tile_mm = c.take<unsigned long long>(6 * (size_t)cap.ntiles);
     D.nM = c.take<double>(Mc);
     D.nS = c.take<double>(3 * Mc);

@@ -511,99 +511,160 @@ __device__ __forceinline__ uint32_t node_id(const ForestDev &f, uint32_t first, 
     return f.base[first] + (uint32_t)__popc(f.mask[first] & ((1u << level) - 1u));
 }
 
-// Mark pass: every node sets bit `level` of mask[first].
+// Mark pass: every node sets bit `level` of mask[first].  The row that starts a
+// leaf keeps the leaf's level (rlam) and end (idx_alt); the boundary row that
+// owns an internal node keeps the node's rows [q, R) (keys_alt), for the fill.
 __global__ void __launch_bounds__(256) k_mark(ForestDev f) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < f.ntot) {
         const Seg sg = seg_of(f, r);
+        uint2 *own = reinterpret_cast<uint2 *>(f.keys_alt);
+        // cube edges: a neighbour sharing fewer than L digits (lcp < L) closes a level-L cube
+        // at once; only longer runs need the key search
+        const int l = f.lcp[r], lr = f.lcp[r + 1];
         // leaf holding r, marked by its first row
-        int lam = leaf_level(f, r, sg);
-        uint32_t a = lam == 0 ? sg.lo : cell_left(f.keys, r, lam, sg.lo);
-        if (a == r) atomicOr(&f.mask[a], 1u << lam);
+        const int lam = leaf_level(f, r, sg);
+        const uint32_t a = lam == 0 ? sg.lo : (l < lam ? r : cell_left(f.keys, r, lam, sg.lo));
+        if (a == r) {
+            atomicOr(&f.mask[a], 1u << lam);
+            f.rlam[r] = (uint8_t)lam;
+            f.idx_alt[r] = lam == 0 ? sg.hi : (lr < lam ? r + 1 : cell_right(f.keys, r, lam, sg.hi));
+        }
         // inner node owned by boundary r (the first split of its cube)
-        int l = f.lcp[r];
+        uint2 node = make_uint2(kNone, kNone);
         if (l >= 0 && l < kMaxLevel) {
-            uint32_t q = cell_left(f.keys, r - 1, l + 1, sg.lo);
+            const uint32_t q = f.lcp[r - 1] <= l ? r - 1 : cell_left(f.keys, r - 1, l + 1, sg.lo);
             if (q == sg.lo || f.lcp[q] < l) {
-                uint32_t R = cell_right(f.keys, r, l, sg.hi);
-                if (R - q > sg.cap) atomicOr(&f.mask[q], 1u << l);
+                const uint32_t R = lr < l ? r + 1 : cell_right(f.keys, r, l, sg.hi);
+                if (R - q > sg.cap) {
+                    atomicOr(&f.mask[q], 1u << l);
+                    node = make_uint2(q, R);
+                }
             }
         }
+        own[r] = node;
     }
 }
 
-// Fill pass: node records at their preorder ids and child links.
+constexpr uint32_t kInner = 0xFFFFFFFFu;   // nchild of an internal node until its children are linked
+
+// Fill pass: node records (level, first rows, count) at their preorder ids.
 __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < f.ntot) {
         const uint32_t s = f.segid[r];
-        const Seg sg = seg_of(f, r);
-        int lam = leaf_level(f, r, sg);
-        uint32_t a = lam == 0 ? sg.lo : cell_left(f.keys, r, lam, sg.lo);
-        if (a == r) {
-            uint32_t b = lam == 0 ? sg.hi : cell_right(f.keys, r, lam, sg.hi);
-            uint32_t g = node_id(f, a, lam);
-            f.nlevel[g] = (uint8_t)lam;
-            f.nfirst[g] = a;
-            f.ncount[g] = b - a;
-            f.nchild[g] = 0;
-            if (a == sg.lo && (f.mask[a] & ((1u << lam) - 1u)) == 0) {
+        const uint32_t lo = f.seg[s].start;
+        const uint32_t m = f.mask[r];
+        const uint2 node = reinterpret_cast<const uint2 *>(f.keys_alt)[r];
+        if (node.x != kNone) {
+            // internal node: a later boundary owns it; its first row q carries the mask bit
+            const uint32_t q = node.x;
+            const int l = f.lcp[r];
+            const uint32_t g = node_id(f, q, l);
+            f.nlevel[g] = (uint8_t)l;
+            f.nfirst[g] = q;
+            f.ncount[g] = node.y - q;
+            f.nchild[g] = kInner;
+            if (q == lo && (f.mask[q] & ((1u << l) - 1u)) == 0) {
                 f.nparent[g] = kNone;
                 f.ncrank[g] = s;
                 f.st[s].nbase = g;
             }
         }
-        int l = f.lcp[r];
-        if (l >= 0 && l < kMaxLevel) {
-            uint32_t q = cell_left(f.keys, r - 1, l + 1, sg.lo);
-            if (q == sg.lo || f.lcp[q] < l) {
-                uint32_t R = cell_right(f.keys, r, l, sg.hi);
-                if (R - q > sg.cap) {
-                    uint32_t g = node_id(f, q, l);
-                    f.nlevel[g] = (uint8_t)l;
-                    f.nfirst[g] = q;
-                    f.ncount[g] = R - q;
-                    if (q == sg.lo && (f.mask[q] & ((1u << l) - 1u)) == 0) {
-                        f.nparent[g] = kNone;
-                        f.ncrank[g] = s;
-                        f.st[s].nbase = g;
-                    }
-                    // children: the level-(l+1) cubes partitioning [q, R)
-                    uint32_t c0 = q, k = 0;
-                    while (c0 < R && k < 8) {
-                        uint32_t c1 = cell_right(f.keys, c0, l + 1, R);
-                        uint32_t c = f.base[c0] + (uint32_t)__popc(f.mask[c0] & ((2u << l) - 1u));
-                        f.nparent[c] = g;
-                        f.ncrank[c] = k;
-                        ++k;
-                        c0 = c1;
-                    }
-                    f.nchild[g] = k;
+        if (m != 0) {
+            // the leaf starting at r, if any: the deepest node starting at r
+            const int lam = f.rlam[r];
+            if (lam > kMaxLevel || m >> lam != 1u) {
+                atomicOr(f.err, kErrTree);   // the deepest node starting at a row must be its leaf
+            } else {
+                const uint32_t g = node_id(f, r, lam);
+                f.nlevel[g] = (uint8_t)lam;
+                f.nfirst[g] = r;
+                f.ncount[g] = f.idx_alt[r] - r;
+                f.nchild[g] = 0;
+                if (r == lo && (m & ((1u << lam) - 1u)) == 0) {
+                    f.nparent[g] = kNone;
+                    f.ncrank[g] = s;
+                    f.st[s].nbase = g;
                 }
             }
         }
     }
 }
 
-// Walk slots: roots take slots [0, nseg); the children of node g take
-// [nseg + cs[g], nseg + cs[g] + nchild[g]) in octant order.
-__global__ void k_slots(ForestDev f) {
-    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t mtot = f.base[f.ntot];
-    if (g >= mtot) return;
-    uint32_t p = f.nparent[g];
-    uint32_t rk = f.ncrank[g];
-    uint32_t sl;
-    if (p == kNone) {
-        sl = rk;
-        if (rk >= f.nseg) { atomicOr(f.err, kErrTree); return; }
-    } else {
-        if (p >= mtot || rk >= 8) { atomicOr(f.err, kErrTree); return; }
-        sl = f.nseg + f.cs[p] + rk;
+// Child links.  In depth-first preorder the first child of internal node g is
+// g + 1 and each next sibling is the first node starting at the row after the
+// previous child's rows (base[end]); the walk over them gives each child its
+// parent and octant rank, and g its child count.
+__global__ void __launch_bounds__(256) k_link(ForestDev f) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mtot = f.base[f.ntot];
+    if (g >= mtot || f.nchild[g] != kInner) return;
+    const uint32_t R = f.nfirst[g] + f.ncount[g];
+    uint32_t c = g + 1, k = 0;
+    bool bad = false;
+    for (;;) {
+        if (c >= mtot || k >= 8) { bad = true; break; }
+        f.nparent[c] = g;
+        f.ncrank[c] = k++;
+        const uint32_t a = f.nfirst[c], e = a + f.ncount[c];
+        if (e >= R || e > f.ntot || e <= a) { bad = e != R; break; }
+        c = f.base[e];
     }
-    if (sl >= mtot) { atomicOr(f.err, kErrTree); return; }
-    f.slot_of[g] = sl;
-    f.node_at_slot[sl] = g;
+    if (bad || k < 2) {
+        atomicOr(f.err, kErrTree);
+        k = 0;
+    }
+    f.nchild[g] = k;
+}
+
+// Walk slots: roots take slots [0, nseg); the children of node g take
+// [nseg + cs[g], nseg + cs[g] + nchild[g]) in octant order.  Each block also
+// lists its internal nodes sorted by level (a counting sort in LDS) with the
+// slots the upward pass needs.
+__global__ void __launch_bounds__(256) k_slots(ForestDev f) {
+    __shared__ uint32_t hist[kMaxLevel + 1], start[kMaxLevel + 2];
+    if (threadIdx.x <= kMaxLevel) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mtot = f.base[f.ntot];
+    int lvl = -1;
+    uint32_t rank = 0;
+    uint4 entry = make_uint4(0, 0, 0, 0);
+    if (g < mtot) {
+        const uint32_t p = f.nparent[g];
+        const uint32_t rk = f.ncrank[g];
+        uint32_t sl = kNone;
+        if (p == kNone) {
+            if (rk < f.nseg) sl = rk;
+        } else if (p < mtot && rk < 8) {
+            sl = f.nseg + f.cs[p] + rk;
+        }
+        if (sl >= mtot) {
+            atomicOr(f.err, kErrTree);
+        } else {
+            f.slot_of[g] = sl;
+            const uint32_t nc = f.nchild[g];
+            if (nc != 0) {
+                lvl = f.nlevel[g];
+                rank = atomicAdd(&hist[lvl], 1u);
+                entry = make_uint4(sl, f.nseg + f.cs[g], nc, 0u);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int l = 0; l <= kMaxLevel; ++l) {
+            start[l] = run;
+            run += hist[l];
+        }
+        start[kMaxLevel + 1] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel + 1)
+        f.blk_lvl[(size_t)blockIdx.x * (kMaxLevel + 2) + threadIdx.x] = (uint16_t)start[threadIdx.x];
+    if (lvl >= 0) f.lvl_list[(size_t)blockIdx.x * blockDim.x + start[lvl] + rank] = entry;
 }
 
 __global__ void k_seg_nodes(ForestDev f) {
@@ -641,12 +702,12 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
     if (e != hipSuccess) return e;
     e = launch_fill_u32(f.ncrank, kNone, f.mcap, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(f.node_at_slot, kNone, f.mcap, s);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, f);
+    const unsigned mb = (f.mcap + 255) / 256;
+    hipLaunchKernelGGL(k_link, dim3(mb), dim3(256), 0, s, f);
     e = scan_exclusive(f.nchild, f.mcap, f.cs, f.scan_tmp, 0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_slots, dim3((f.mcap + 255) / 256), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_slots, dim3(mb), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_seg_nodes, dim3(segb), dim3(256), 0, s, f);
     return hipGetLastError();
 }
@@ -655,15 +716,16 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
 
 // Upward pass, level by level from the deepest level: a launch sums the leaves
 // (particles in key order), then one launch per level sums each internal node's
-// children in octant order.  The kernel boundaries order the levels; no
-// device-scope fences are needed.
+// children in octant order, over that level's node list.  The kernel
+// boundaries order the levels; no device-scope fences are needed.
 
 __global__ void k_up_leaf(ForestDev f) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t mtot = f.base[f.ntot];
     if (g >= mtot || f.nchild[g] != 0) return;
     const uint32_t a = f.nfirst[g], b = a + f.ncount[g];
-    if (a >= f.ntot || b > f.ntot || b <= a) { atomicOr(f.err, kErrTree); return; }
+    const uint32_t sl = f.slot_of[g];
+    if (a >= f.ntot || b > f.ntot || b <= a || sl >= mtot) { atomicOr(f.err, kErrTree); return; }
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     for (uint32_t r = a; r < b; ++r) {
         const double m = f.smass[r];
@@ -672,33 +734,37 @@ __global__ void k_up_leaf(ForestDev f) {
         Sy = __dadd_rn(Sy, __dmul_rn(m, f.spos[3 * (size_t)r + 1]));
         Sz = __dadd_rn(Sz, __dmul_rn(m, f.spos[3 * (size_t)r + 2]));
     }
-    f.nM[g] = M;
-    f.nS[3 * (size_t)g] = Sx;
-    f.nS[3 * (size_t)g + 1] = Sy;
-    f.nS[3 * (size_t)g + 2] = Sz;
+    f.uM[sl] = M;
+    f.uS[3 * (size_t)sl] = Sx;
+    f.uS[3 * (size_t)sl + 1] = Sy;
+    f.uS[3 * (size_t)sl + 2] = Sz;
 }
 
-__global__ void k_up_level(ForestDev f, int level) {
+// One wavefront per block of 256 node ids: its level-`level` internal nodes,
+// whose children occupy consecutive walk slots.
+__global__ void __launch_bounds__(256) k_up_level(ForestDev f, int level, uint32_t nblk) {
+    const uint32_t lane = threadIdx.x & 63;
     const uint32_t mtot = f.base[f.ntot];
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < mtot; g += gridDim.x * blockDim.x) {
-        if (f.nlevel[g] != level || f.nchild[g] == 0) continue;
-        const uint32_t nc = f.nchild[g], c0 = f.nseg + f.cs[g];
-        if (nc < 2 || nc > 8 || c0 + nc > mtot) { atomicOr(f.err, kErrTree); continue; }
-        double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
-        bool bad = false;
-        for (uint32_t k = 0; k < nc; ++k) {
-            const uint32_t c = f.node_at_slot[c0 + k];
-            if (c >= mtot) { bad = true; break; }
-            M = __dadd_rn(M, f.nM[c]);
-            Sx = __dadd_rn(Sx, f.nS[3 * (size_t)c]);
-            Sy = __dadd_rn(Sy, f.nS[3 * (size_t)c + 1]);
-            Sz = __dadd_rn(Sz, f.nS[3 * (size_t)c + 2]);
+    for (uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += gridDim.x * 4) {
+        const uint16_t *bl = f.blk_lvl + (size_t)b * (kMaxLevel + 2);
+        const uint32_t begin = bl[level], end = bl[level + 1];
+        for (uint32_t i = begin + lane; i < end; i += 64) {
+            const uint4 e = f.lvl_list[(size_t)b * 256 + i];
+            const uint32_t sl = e.x, c0 = e.y, nc = e.z;
+            if (sl >= mtot || nc < 2 || nc > 8 || c0 + nc > mtot) { atomicOr(f.err, kErrTree); continue; }
+            double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+            for (uint32_t k = 0; k < nc; ++k) {
+                const size_t c = c0 + k;
+                M = __dadd_rn(M, f.uM[c]);
+                Sx = __dadd_rn(Sx, f.uS[3 * c]);
+                Sy = __dadd_rn(Sy, f.uS[3 * c + 1]);
+                Sz = __dadd_rn(Sz, f.uS[3 * c + 2]);
+            }
+            f.uM[sl] = M;
+            f.uS[3 * (size_t)sl] = Sx;
+            f.uS[3 * (size_t)sl + 1] = Sy;
+            f.uS[3 * (size_t)sl + 2] = Sz;
         }
-        if (bad) { atomicOr(f.err, kErrTree); continue; }
-        f.nM[g] = M;
-        f.nS[3 * (size_t)g] = Sx;
-        f.nS[3 * (size_t)g + 1] = Sy;
-        f.nS[3 * (size_t)g + 2] = Sz;
     }
 }
 
@@ -707,12 +773,18 @@ __global__ void k_records(ForestDev f) {
     uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t mtot = f.base[f.ntot];
     if (g >= mtot) return;
-    double M = f.nM[g];
+    const uint32_t sl = f.slot_of[g];
+    if (sl >= mtot) {
+        atomicOr(f.err, kErrTree);
+        return;
+    }
+    const double M = f.uM[sl];
     double c[3];
     for (int d = 0; d < 3; ++d) {
-        c[d] = f.nS[3 * (size_t)g + d] / M;
+        c[d] = f.uS[3 * (size_t)sl + d] / M;
         f.nS[3 * (size_t)g + d] = c[d];
     }
+    f.nM[g] = M;
     const uint32_t sid = f.segid[f.nfirst[g]];
     const SegDesc &sd = f.seg[sid];
     const SegState &st = f.st[sid];
@@ -720,8 +792,7 @@ __global__ void k_records(ForestDev f) {
     const uint32_t nc = f.nchild[g];
     const uint32_t link = nc ? f.nseg + f.cs[g] : f.nfirst[g];
     const uint32_t cnt = nc ? nc : (f.ncount[g] | kLeafBit);
-    const uint32_t sl = f.slot_of[g];
-    if (sl >= mtot || (nc && (nc < 2 || nc > 8 || link + nc > mtot)) ||
+    if ((nc && (nc < 2 || nc > 8 || link + nc > mtot)) ||
         (!nc && (link >= f.ntot || f.ncount[g] == 0 || link + f.ncount[g] > f.ntot))) {
         atomicOr(f.err, kErrTree);
         return;
@@ -781,10 +852,11 @@ __global__ void k_records(ForestDev f) {
 hipError_t launch_upward(const ForestDev &f, hipStream_t s) {
     const unsigned mb = (f.mcap + 255) / 256;
     hipLaunchKernelGGL(k_up_leaf, dim3(mb), dim3(256), 0, s, f);
-    unsigned lb = (f.mcap + 255) / 256;
-    if (lb > 2048) lb = 2048;
+    // one wavefront per list block; the lists cover the node ids [0, mcap) in blocks of 256
+    const unsigned nblk = mb;
+    const unsigned lb = (nblk + 3) / 4 < 1024 ? (nblk + 3) / 4 : 1024;
     for (int l = kMaxLevel - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_up_level, dim3(lb), dim3(256), 0, s, f, l);
+        hipLaunchKernelGGL(k_up_level, dim3(lb), dim3(256), 0, s, f, l, nblk);
     hipLaunchKernelGGL(k_records, dim3(mb), dim3(256), 0, s, f);
     return hipGetLastError();
 }

@@ -99,7 +99,12 @@ struct ForestDev {
     uint32_t *nchild;           // per node (scan input: number of children)
     uint32_t *nfirst, *ncount, *nparent, *ncrank;
     uint32_t *cs;               // exclusive scan of nchild
-    uint32_t *slot_of, *node_at_slot;
+    uint32_t *slot_of;          // walk slot of each node
+    uint4 *lvl_list;            // per block of 256 node ids: its internal nodes sorted by level,
+                                //   as (slot, first child slot, children, 0)
+    uint16_t *blk_lvl;          // per such block: start of each level in its list (23 entries)
+    double *uM, *uS;            // upward pass: mass and mass-weighted position sums by walk slot
+    uint8_t *rlam;              // per row that starts a leaf: the leaf's level
     unsigned long long *tile_mm; // per tile: integer images of the bbox min (3) and max (3)
     double *nM, *nS;            // node mass, centre of mass (FP64; S then com in place)
     WRec32 *w32;
@@ -147,50 +152,74 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
+// Edge of row r's level-`level` cube within sorted keys [lo, hi): RIGHT gives one
+// past its last row, otherwise its first row.  Rows of one cube are contiguous,
+// so membership is monotone in the distance from r; the search probes up to 8
+// rows per round (independent loads): first at power-of-two distances in
+// growing batches, then at 8 evenly spaced points of the bracketing interval,
+// so a cube of n rows costs a few dependent rounds (about 2 + log_9 n for big
+// cubes) instead of 2 log_2 n dependent loads.
+template <bool RIGHT>
+struct CellProbe {
+    const uint64_t *K;
+    uint32_t r, avail;   // rows available beyond r in the search direction
+    int sh;
+    uint64_t P;
+    __device__ __forceinline__ bool inside(uint32_t d) const {
+        return d <= avail && (K[RIGHT ? r + d : r - d] >> sh) == P;
+    }
+    // One round of NE probes at distances 2^E0 .. 2^(E0+NE-1); true once the edge is bracketed.
+    template <int E0, int NE>
+    __device__ __forceinline__ bool round(uint32_t &good, uint32_t &bad) const {
+        int nin = 0;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) nin += inside(1u << (E0 + k)) ? 1 : 0;   // the inside probes form a prefix
+        if (nin > 0) good = 1u << (E0 + nin - 1);
+        if (nin < NE) {
+            const uint32_t d = 1u << (E0 + nin);
+            if (d < bad) bad = d;
+            return true;
+        }
+        return false;
+    }
+};
+
+template <bool RIGHT>
+__device__ __noinline__ uint32_t cell_edge(const uint64_t *K, uint32_t r, int level, uint32_t lo, uint32_t hi) {
+    if (level <= 0) return RIGHT ? hi : lo;
+    const int sh = 3 * (kMaxLevel - level);
+    const CellProbe<RIGHT> pb{K, r, RIGHT ? hi - 1 - r : r - lo, sh, K[r] >> sh};
+    // distances from r: inside(good) holds (good = 0 is r itself), inside(bad) does not
+    uint32_t good = 0, bad = pb.avail + 1;
+    (void)(pb.template round<0, 2>(good, bad) || pb.template round<2, 4>(good, bad) ||
+           pb.template round<6, 8>(good, bad) || pb.template round<14, 8>(good, bad) ||
+           pb.template round<22, 8>(good, bad) || pb.template round<30, 1>(good, bad));
+    while (bad - good > 1) {
+        const uint32_t span = bad - good;
+        int nin = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t o = span <= 9 ? (uint32_t)(k + 1) : (uint32_t)((uint64_t)span * (k + 1) / 9);
+            nin += (o < span && pb.inside(good + o)) ? 1 : 0;
+        }
+        const uint32_t g0 = good;
+        if (nin > 0) good = g0 + (span <= 9 ? (uint32_t)nin : (uint32_t)((uint64_t)span * nin / 9));
+        if (nin < 8) {
+            const uint32_t o = span <= 9 ? (uint32_t)(nin + 1) : (uint32_t)((uint64_t)span * (nin + 1) / 9);
+            if (o < span) bad = g0 + o;
+        }
+    }
+    return RIGHT ? r + bad : r - good;
+}
+
 // First row q in [lo, r] whose key shares r's level-`level` cube (keys sorted on [lo, hi)).
 __device__ inline uint32_t cell_left(const uint64_t *K, uint32_t r, int level, uint32_t lo) {
-    if (level <= 0) return lo;
-    const int sh = 3 * (kMaxLevel - level);
-    const uint64_t P = K[r] >> sh;
-    uint32_t good = r, bad, step = 1;
-    for (;;) {
-        if (good - lo < step) {
-            if ((K[lo] >> sh) == P) return lo;
-            bad = lo;
-            break;
-        }
-        uint32_t q = good - step;
-        if ((K[q] >> sh) == P) { good = q; step <<= 1; }
-        else { bad = q; break; }
-    }
-    while (good - bad > 1) {
-        uint32_t mid = bad + (good - bad) / 2;
-        if ((K[mid] >> sh) == P) good = mid; else bad = mid;
-    }
-    return good;
+    return cell_edge<false>(K, r, level, lo, 0u);
 }
 
 // One past the last row q in [r, hi) whose key shares r's level-`level` cube.
 __device__ inline uint32_t cell_right(const uint64_t *K, uint32_t r, int level, uint32_t hi) {
-    if (level <= 0) return hi;
-    const int sh = 3 * (kMaxLevel - level);
-    const uint64_t P = K[r] >> sh;
-    uint32_t good = r, bad, step = 1;
-    for (;;) {
-        if (hi - 1 - good < step) {
-            if ((K[hi - 1] >> sh) == P) return hi;
-            bad = hi - 1;
-            break;
-        }
-        uint32_t q = good + step;
-        if ((K[q] >> sh) == P) { good = q; step <<= 1; }
-        else { bad = q; break; }
-    }
-    while (bad - good > 1) {
-        uint32_t mid = good + (bad - good) / 2;
-        if ((K[mid] >> sh) == P) good = mid; else bad = mid;
-    }
-    return good + 1;
+    return cell_edge<true>(K, r, level, 0u, hi);
 }
 
 // ------------------------------------------------------ launcher prototypes ---
