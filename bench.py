@@ -30,6 +30,25 @@ METRIC = "BH force-evals Mparticles/s at theta=0.5, N=1M (FP32 vs FP64); served 
 FP32_PEAK = 157.3e12     # MI355X vector FP32 (packed issue)
 FP64_PEAK = 78.6e12      # MI355X vector FP64
 FLOPS_PER_INTERACTION = 20
+TRAFFIC_SUMMARY = ROOT / "profiles" / "hbm_traffic_plummer_1M.md"
+WALK_SOURCE = ROOT / "paper_1109_5190_amd" / "csrc" / "bh_walk.hip"
+
+
+def walk_traffic(n):
+    """HBM bytes per FP32 walk launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel), or None when the summary was taken on
+    another workload size or on a different walk source."""
+    import hashlib
+    import re
+    try:
+        text = TRAFFIC_SUMMARY.read_text()
+        sha = hashlib.sha256(WALK_SOURCE.read_bytes()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"bench-traffic: kernel=k_walk32 n=(\d+) bytes=(\d+) source-sha256=([0-9a-f]+)", text)
+    if not m or int(m.group(1)) != n or m.group(3) != sha:
+        return None
+    return int(m.group(2))
 
 
 def parse():
@@ -186,7 +205,8 @@ def main():
                                f"leaf_cap={a.leaf_cap}, KDK dt={a.dt} with tree rebuild every step",
                    "n": a.n, "theta": a.theta, "eps": a.eps, "leaf_cap": a.leaf_cap, "dt": a.dt},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": walk_traffic(a.n) if head == "fp32" else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated)",
                      "kernel": f"k_walk32 ({FLOPS_PER_INTERACTION} flops x {r['interactions']} interactions "
                                f"per launch / {r['ms_walk']:.3f} ms)"},
         "walk_only": {"ms": r["ms_walk"], "mparticles_per_s": a.n / (r["ms_walk"] * 1e-3) / 1e6,
