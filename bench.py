@@ -69,7 +69,152 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-precision", default="fp32")
+    ap.add_argument("--workload", choices=("plummer1m", "sweep", "batch"), default="plummer1m",
+                    help="plummer1m: the headline line; sweep: the two-sphere and cube systems of 2^22 over "
+                         "theta; batch: 512 simulations as one forest (each prints its own JSON line)")
+    ap.add_argument("--sample", type=int, default=2048, help="oracle targets per error check (sweep, batch)")
     return ap.parse_args()
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _errors(acc, ref):
+    import numpy as np
+    rms = float(np.sqrt(((acc - ref) ** 2).sum() / (ref ** 2).sum()))
+    den = np.linalg.norm(ref, axis=1)
+    ok = den > 0
+    mx = float((np.linalg.norm(acc - ref, axis=1)[ok] / den[ok]).max()) if ok.any() else 0.0
+    return rms, mx
+
+
+def sweep(a, bh, torch):
+    """Theta sweep on the two-sphere system (2 x 2^21) and the uniform cube (2^22), eps = 0.005:
+    one force evaluation (build + upward + walk) per theta and precision, timed with events on the
+    library's stream, and its error against the oracle on sampled targets."""
+    import numpy as np
+
+    import icgen
+    import oracle
+    dev = torch.device("cuda:0")
+    ctx = bh.Context(0)
+    stream = torch.cuda.current_stream(dev)
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+    systems = {"two_spheres": lambda: icgen.two_plummer(1 << 21, 3, 4), "cube": lambda: icgen.uniform_cube(1 << 22, 5)}
+    for name, make in systems.items():
+        s = make()
+        pos, mass = torch.tensor(s.pos, device=dev), torch.tensor(s.mass, device=dev)
+        T = oracle.Tree(s.pos, s.mass, a.leaf_cap)
+        rng = np.random.default_rng(21)
+        tg = np.sort(rng.choice(s.n, min(a.sample, s.n), replace=False)).astype(np.int64)
+        tgd = torch.tensor(tg, device=dev)
+        for theta in (0.3, 0.5, 0.7, 1.0):
+            ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores)
+            inter = None
+            for prec in ("fp32", "fp64"):
+                p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec)
+                t = bh.Tree(ctx, pos, mass, p).upward()
+                acc = t.forces()
+                if inter is None:
+                    tot = t.forces_stats()["totals"]
+                    inter = tot["n_mono"] + tot["n_p2p"]
+                torch.cuda.synchronize()
+                e0, e1 = _events(torch)
+                w0, w1 = _events(torch)
+                reps = 3
+                e0.record(stream)
+                for _ in range(reps):
+                    t2 = bh.Tree(ctx, pos, mass, p).upward()
+                    t2.forces(acc)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                w0.record(stream)
+                for _ in range(reps):
+                    t.forces(acc)
+                w1.record(stream)
+                torch.cuda.synchronize()
+                ms_eval = e0.elapsed_time(e1) / reps
+                ms_walk = w0.elapsed_time(w1) / reps
+                rms, mx = _errors(acc[tgd].cpu().numpy(), ref["acc"])
+                peak = 157.3e12 if prec == "fp32" else 78.6e12
+                rows.append({"system": name, "n": s.n, "theta": theta, "precision": prec,
+                             "ms_force_eval": ms_eval, "mparticles_per_s": s.n / (ms_eval * 1e-3) / 1e6,
+                             "ms_walk": ms_walk, "interactions_per_particle": inter / s.n,
+                             "walk_tflops": 20 * inter / (ms_walk * 1e-3) / 1e12,
+                             "walk_frac_of_peak": 20 * inter / (ms_walk * 1e-3) / peak,
+                             "rms_rel_vs_oracle": rms, "max_rel_vs_oracle": mx})
+                print(f"# {name} theta={theta} {prec}: eval {ms_eval:.3f} ms walk {ms_walk:.3f} ms "
+                      f"rms {rms:.2e} max {mx:.2e}", file=sys.stderr, flush=True)
+                del t, t2
+        del T
+    return {"metric": "theta sweep: force evaluations Mparticles/s and error vs the FP64 oracle",
+            "unit": "Mparticles/s", "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "two unit-mass Plummer spheres of 2^21 at +-(5,0,0), seeds 3/4; uniform cube "
+                                   "2^22 in [-1,1]^3, masses U[0.5,1.5]/N, seed 5; eps 0.005; leaf_cap "
+                                   f"{a.leaf_cap}", "error_sample": f"{a.sample} random targets per system"},
+            "results": rows}
+
+
+def batch(a, bh, torch):
+    """512 Plummer simulations (N log-uniform in [1024, 262144], theta from {0.4, 0.5, 0.7},
+    eps 0.01, dt 1e-3) as one forest in FP32: launch shape autotuned, then 20 KDK steps replayed
+    from one recorded HIP graph; throughput in particle-steps per second."""
+    import numpy as np
+
+    import icgen
+    import oracle
+    dev = torch.device("cuda:0")
+    ctx = bh.Context(0)
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.time()
+    inst = icgen.batch_instances(512, 6)
+    systems = [icgen.plummer(n, seed) for n, _, seed in inst]
+    cat = icgen.concat(*systems)
+    print(f"# generated {cat.n} particles in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    ns = [n for n, _, _ in inst]
+    plist = [bh.params(th, 0.01, 1.0, a.leaf_cap, "fp32") for _, th, _ in inst]
+    pos = torch.tensor(cat.pos, device=dev)
+    vel = torch.tensor(cat.vel, device=dev)
+    mass = torch.tensor(cat.mass, device=dev)
+    forest = bh.Forest(ctx, ns, plist, pos, vel, mass)
+    waves, tune_ms = forest.autotune()
+    acc0 = forest.acc.cpu().numpy()
+    dts = [1e-3] * len(ns)
+    forest.step_graph(1, dts)      # records the graph and warms up
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    steps = 20
+    e0.record(stream)
+    forest.step_graph(steps, dts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    total = int(sum(ns))
+    # error at the initial positions on stratified instances
+    cores = len(os.sched_getaffinity(0))
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    order = np.argsort(ns)
+    pick = order[np.linspace(0, len(ns) - 1, 8).astype(int)]
+    rng = np.random.default_rng(22)
+    a_all, r_all = [], []
+    for k in pick:
+        sk = systems[k]
+        tg = np.sort(rng.choice(sk.n, min(256, sk.n), replace=False)).astype(np.int64)
+        ref = oracle.forces(sk.pos, sk.mass, theta=inst[k][1], eps=0.01, targets=tg, nthreads=cores)
+        a_all.append(acc0[offs[k]:offs[k + 1]][tg])
+        r_all.append(ref["acc"])
+    rms, mx = _errors(np.concatenate(a_all), np.concatenate(r_all))
+    return {"metric": "batch: particle-steps/s of 512 simulations in one forest (FP32, HIP graph)",
+            "value": total * steps / (ms * 1e-3), "unit": "particle-steps/s", "n_gpus": 1, "steps": steps,
+            "ms_per_step": ms / steps, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "512 Plummer instances, N log-uniform in [1024, 262144] (seed 6), theta from "
+                                   "{0.4, 0.5, 0.7}, eps 0.01, dt 1e-3, KDK with a rebuild every step",
+                       "total_particles": total, "leaf_cap": a.leaf_cap},
+            "autotune": {"walk_waves_per_workgroup": waves, "walk_ms_by_waves": tune_ms},
+            "force_error_vs_oracle": {"rms_rel": rms, "max_rel": mx,
+                                      "sample": "256 targets on each of 8 instances stratified by N, initial positions"}}
 
 
 def serve(a, bh, ctx, torch):
@@ -124,6 +269,12 @@ def main():
     import icgen
     import paper_1109_5190_amd as bh
 
+    if a.workload == "sweep":
+        print(json.dumps(sweep(a, bh, torch)))
+        return
+    if a.workload == "batch":
+        print(json.dumps(batch(a, bh, torch)))
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     s = icgen.plummer(a.n, a.seed)

@@ -185,6 +185,15 @@ bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *f, double *pot);
 /* Record one step of the forest as a HIP graph (on first call) and replay it
  * nsteps times. */
 bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *f, int32_t nsteps, const double *dt);
+/* SYNC.  Autotuner of the forest's walk launch shape: builds the tree at the
+ * current positions, times the force walk (two launches after a warm-up, HIP
+ * events on the context's stream) with 1, 2, 4 and 8 wavefronts per workgroup
+ * (one 64-body group per wavefront) and keeps the fastest for this forest's
+ * later evaluations; a recorded step graph is re-recorded.  The shape changes
+ * no result.  waves_out (nullable): the chosen count; ms_out (nullable, host
+ * array of 4): measured walk times in ms in the order 1, 2, 4, 8.  acc is
+ * refreshed as a side effect (forces at the current positions). */
+bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *f, int32_t *waves_out, double *ms_out);
 /* SYNC.  Per-simulation energies at the current positions: out_KW[2 s] = K_s,
  * out_KW[2 s + 1] = W_s (host array of 2 n_sims); also refreshes acc. */
 bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *f, double *out_KW);

@@ -79,6 +79,7 @@ _SIGS = {
     "bh_forest_step": ([_VP, _VP, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_forces": ([_VP, _VP, _VP], C.c_int),
     "bh_forest_step_graph": ([_VP, _VP, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "bh_forest_autotune": ([_VP, _VP, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
     "bh_forest_energy": ([_VP, _VP, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_destroy": ([_VP, _VP], C.c_int),
     "bh_ic_generate": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP], C.c_int),
@@ -334,6 +335,14 @@ class Forest:
 
     def step_graph(self, nsteps, dt):
         _check(lib().bh_forest_step_graph(self.ctx.h, self.h, int(nsteps), self._dt(dt)))
+
+    def autotune(self):
+        """Times the walk with 1, 2, 4 and 8 wavefronts per workgroup at the current
+        positions and keeps the fastest.  Returns (waves, {waves: ms})."""
+        w = C.c_int32()
+        ms = (C.c_double * 4)()
+        _check(lib().bh_forest_autotune(self.ctx.h, self.h, C.byref(w), ms))
+        return int(w.value), {k: float(ms[i]) for i, k in enumerate((1, 2, 4, 8))}
 
     def forces(self, pot=None):
         _check(lib().bh_forest_forces(self.ctx.h, self.h, _ptr(pot)))

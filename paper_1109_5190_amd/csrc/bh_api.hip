@@ -229,7 +229,7 @@ bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, d
     if (!s) s = F.ctx->stream;
     HIPCHK(launch_build(F.dev, pos, mass, s));
     HIPCHK(launch_upward(F.dev, s));
-    HIPCHK(launch_walk(F.dev, false, want_pot, acc, pot, nullptr, nullptr, nullptr, s));
+    HIPCHK(launch_walk(F.dev, false, want_pot, acc, pot, nullptr, nullptr, nullptr, s, F.walk_waves));
     return BH_OK;
 }
 
@@ -342,7 +342,8 @@ bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
 bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces");
-    HIPCHK(launch_walk(t->F.dev, false, pot != nullptr, acc, pot, nullptr, nullptr, nullptr, ctx->stream));
+    HIPCHK(launch_walk(t->F.dev, false, pot != nullptr, acc, pot, nullptr, nullptr, nullptr, ctx->stream,
+                       t->F.walk_waves));
     return BH_OK;
 }
 
@@ -351,7 +352,8 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
     HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
-    HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream));
+    HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream,
+                       t->F.walk_waves));
     unsigned long long h[8];
     HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     bh_status st = bh_forest_check_err(t->F);
@@ -560,6 +562,59 @@ bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const
         HIPCHK(ie);
     }
     for (int32_t k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(fo->graph, s));
+    return BH_OK;
+}
+
+namespace {
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+}  // namespace
+
+bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, int32_t *waves_out, double *ms_out) {
+    if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    hipStream_t s = ctx->stream;
+    ForestHost &F = fo->F;
+    HIPCHK(launch_build(F.dev, fo->pos, fo->mass, s));
+    HIPCHK(launch_upward(F.dev, s));
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    constexpr int kReps = 2;
+    float best = 0.0f;
+    int bw = F.walk_waves;
+    for (int k = 0; k < 4; ++k) {
+        const int w = kWalkWaves[k];
+        HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));   // warm-up
+        HIPCHK(hipEventRecord(ev.a, s));
+        for (int r = 0; r < kReps; ++r)
+            HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));
+        HIPCHK(hipEventRecord(ev.b, s));
+        HIPCHK(hipEventSynchronize(ev.b));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+        ms /= kReps;
+        if (ms_out) ms_out[k] = ms;
+        if (k == 0 || ms < best) {
+            best = ms;
+            bw = w;
+        }
+    }
+    bh_status st = bh_forest_check_err(F);
+    if (st != BH_OK) return st;
+    if (bw != F.walk_waves) {
+        F.walk_waves = bw;
+        if (fo->graph) {   // recorded with the previous launch shape
+            HIPCHK(hipGraphExecDestroy(fo->graph));
+            fo->graph = nullptr;
+        }
+    }
+    fo->have_acc = true;
+    if (waves_out) *waves_out = bw;
     return BH_OK;
 }
 

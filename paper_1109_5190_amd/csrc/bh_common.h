@@ -11,7 +11,7 @@ constexpr int kTile = 4096;            // particles per sort / bbox tile
 constexpr int kTileThreads = 256;
 constexpr int kItems = kTile / kTileThreads;   // 16 keys per thread in the sort
 constexpr int kGroup = 64;             // walk targets per wavefront
-constexpr int kWalkThreads = 256;      // 4 wavefronts per block
+constexpr int kWalkWaves[4] = {1, 2, 4, 8};   // walk launch shapes: wavefronts per block
 constexpr int kStackMax = 160;         // >= 1 + 7 * 21 entries of (child block, lane mask)
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
@@ -229,7 +229,7 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
                         hipStream_t s);                          // bbox .. tree topology
 hipError_t launch_upward(const ForestDev &f, hipStream_t s);     // masses, centres, walk records
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
-                       int64_t *n_p2p, uint64_t *hash, hipStream_t s);
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves = 4);
 // phase_mask 0: every simulation; else only those whose SegDesc.phase has a bit of the mask.
 hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s);
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);

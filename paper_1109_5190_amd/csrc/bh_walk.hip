@@ -26,7 +26,6 @@ namespace bh {
 
 constexpr float kU32 = 5.9604644775390625e-8f;   // 2^-24
 constexpr uint32_t kFlushWork = 64;              // pair terms (upper bound) between Kahan folds
-constexpr int kWaves = kWalkThreads / 64;
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
@@ -105,12 +104,12 @@ struct WaveLds32 {
 // repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
 // into FP32 partial sums that are folded into Kahan-compensated totals after
 // at most 64 terms.
-template <bool STATS, bool POT>
-__global__ void __launch_bounds__(kWalkThreads) k_walk32(ForestDev f, WalkOut out) {
-    __shared__ WaveLds32 lds_all[kWaves];
+template <bool STATS, bool POT, int W>
+__global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
+    __shared__ WaveLds32 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveLds32 &L = lds_all[wave];
-    const uint32_t gi = blockIdx.x * kWaves + wave;
+    const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
     const GroupDesc gd = f.groups[gi];
@@ -349,12 +348,12 @@ struct WaveLds64 {
     double4 pst[64];
 };
 
-template <bool STATS, bool POT>
-__global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut out) {
-    __shared__ WaveLds64 lds_all[kWaves];
+template <bool STATS, bool POT, int W>
+__global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
+    __shared__ WaveLds64 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveLds64 &L = lds_all[wave];
-    const uint32_t gi = blockIdx.x * kWaves + wave;
+    const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
     const GroupDesc gd = f.groups[gi];
@@ -518,29 +517,42 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk64(ForestDev f, WalkOut ou
     }
 }
 
-hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
-                       int64_t *n_p2p, uint64_t *hash, hipStream_t s) {
-    WalkOut o{acc, pot, n_mono, n_p2p, hash};
-    const unsigned blocks = (f.ngroups + kWaves - 1) / kWaves;
-    if (blocks == 0) return hipSuccess;
-    const dim3 g(blocks), b(kWalkThreads);
+// One walk launch: W wavefronts (one group each) per block.  The launch shape
+// does not change any result (each group's arithmetic is its own); forests
+// pick it by measurement (bh_forest_autotune).
+template <int W>
+static void launch_walk_w(const ForestDev &f, bool stats, bool want_pot, const WalkOut &o, hipStream_t s) {
+    const unsigned blocks = (f.ngroups + W - 1) / W;
+    const dim3 g(blocks), b(64 * W);
     if (f.has32) {
         if (stats) {
-            if (want_pot) hipLaunchKernelGGL((k_walk32<true, true>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<true, false>), g, b, 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk32<true, true, W>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk32<true, false, W>), g, b, 0, s, f, o);
         } else {
-            if (want_pot) hipLaunchKernelGGL((k_walk32<false, true>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<false, false>), g, b, 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk32<false, true, W>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk32<false, false, W>), g, b, 0, s, f, o);
         }
     }
     if (f.has64) {
         if (stats) {
-            if (want_pot) hipLaunchKernelGGL((k_walk64<true, true>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<true, false>), g, b, 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk64<true, true, W>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk64<true, false, W>), g, b, 0, s, f, o);
         } else {
-            if (want_pot) hipLaunchKernelGGL((k_walk64<false, true>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<false, false>), g, b, 0, s, f, o);
+            if (want_pot) hipLaunchKernelGGL((k_walk64<false, true, W>), g, b, 0, s, f, o);
+            else hipLaunchKernelGGL((k_walk64<false, false, W>), g, b, 0, s, f, o);
         }
+    }
+}
+
+hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves) {
+    WalkOut o{acc, pot, n_mono, n_p2p, hash};
+    if (f.ngroups == 0) return hipSuccess;
+    switch (waves) {
+        case 1: launch_walk_w<1>(f, stats, want_pot, o, s); break;
+        case 2: launch_walk_w<2>(f, stats, want_pot, o, s); break;
+        case 8: launch_walk_w<8>(f, stats, want_pot, o, s); break;
+        default: launch_walk_w<4>(f, stats, want_pot, o, s); break;
     }
     return hipGetLastError();
 }

@@ -136,3 +136,21 @@ def test_device_initial_conditions_match_generator(ctx, kind):
     assert np.allclose(pos.cpu().numpy(), ref.pos, rtol=1e-12, atol=1e-12)
     assert np.allclose(vel.cpu().numpy(), ref.vel, rtol=1e-12, atol=1e-12)
     assert np.allclose(mass.cpu().numpy(), ref.mass, rtol=1e-15, atol=0)
+
+
+def test_autotune_changes_no_result(ctx):
+    """The walk's launch shape is chosen by timing; every shape gives the same bits."""
+    ns = [3000, 700, 12000, 64]
+    plist = [bh.params(0.5, 0.01, precision=pr) for pr in ("fp32", "fp64", "fp32", "fp64")]
+    systems, cat = make_forest_inputs(ns, [41, 42, 43, 44])
+    fo = bh.Forest(ctx, ns, plist, dev(cat.pos), dev(cat.vel), dev(cat.mass))
+    ref = bh.Forest(ctx, ns, plist, dev(cat.pos), dev(cat.vel), dev(cat.mass))
+    a0 = fo.forces().clone()
+    waves, ms = fo.autotune()
+    assert waves in (1, 2, 4, 8) and sorted(ms) == [1, 2, 4, 8] and all(v > 0 for v in ms.values())
+    assert torch.equal(fo.acc, a0)          # the last timed shape (8 waves)
+    assert torch.equal(fo.forces(), a0)     # the chosen shape
+    fo.step_graph(2, 1e-3)
+    ref.step(2, 1e-3)
+    ctx.sync()
+    assert torch.equal(fo.pos, ref.pos) and torch.equal(fo.acc, ref.acc)
