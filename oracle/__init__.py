@@ -25,7 +25,8 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
 
 
 class Params(C.Structure):
-    _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double), ("leaf_cap", C.c_int32)]
+    _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double), ("leaf_cap", C.c_int32),
+                ("quad", C.c_int32)]
 
 
 def build(force: bool = True) -> Path:
@@ -58,6 +59,7 @@ def lib():
         L.or_tree_destroy.argtypes = [C.c_void_p]
         L.or_tree_nn.argtypes = [C.c_void_p]
         L.or_tree_nn.restype = C.c_int64
+        L.or_tree_moments.argtypes = [C.c_void_p, _f64p]
         L.or_tree_export.argtypes = [C.c_void_p, _f64p, C.POINTER(C.c_int32), _u64p, _u32p, _i32p,
                                      _u32p, _u32p, _i32p, _i32p, _f64p, _f64p]
         opt = lambda t: C.c_void_p  # noqa: E731  (nullable array arguments)
@@ -115,8 +117,8 @@ def order(keys_):
     return perm
 
 
-def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1):
-    return Params(float(theta), float(eps), float(G), int(leaf_cap))
+def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, quad=False):
+    return Params(float(theta), float(eps), float(G), int(leaf_cap), int(bool(quad)))
 
 
 class Tree:
@@ -148,8 +150,14 @@ class Tree:
         self.k = int(k.value)
         self.L = 2.0 ** self.k
 
-    def walk(self, theta=0.5, eps=0.01, G=1.0, targets=None, nthreads=0):
-        p = params(theta, eps, G, 1)
+    def moments(self):
+        """Second moments about each node's centre of mass (nn x 6: xx yy zz xy xz yz)."""
+        out = np.zeros((self.nn, 6))
+        lib().or_tree_moments(self._h, out)
+        return out
+
+    def walk(self, theta=0.5, eps=0.01, G=1.0, targets=None, nthreads=0, quad=False):
+        p = params(theta, eps, G, 1, quad)
         t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
         nt = self.n if t is None else t.shape[0]
         acc = np.zeros((nt, 3))
@@ -170,9 +178,9 @@ class Tree:
             self._h = None
 
 
-def forces(pos, mass, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, targets=None, nthreads=0):
+def forces(pos, mass, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, targets=None, nthreads=0, quad=False):
     t = Tree(pos, mass, leaf_cap)
-    return t.walk(theta, eps, G, targets, nthreads)
+    return t.walk(theta, eps, G, targets, nthreads, quad)
 
 
 def direct(pos, mass, eps=0.01, G=1.0, targets=None, nthreads=0):
@@ -187,7 +195,7 @@ def direct(pos, mass, eps=0.01, G=1.0, targets=None, nthreads=0):
     return dict(acc=acc, pot=pot)
 
 
-def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=None, nthreads=0):
+def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=None, nthreads=0, quad=False):
     """Returns (pos, vel, acc, pot) after nsteps leapfrog steps (copies; inputs untouched)."""
     pos = _f64(pos, (-1, 3)).copy()
     vel = _f64(vel, (-1, 3)).copy()
@@ -195,7 +203,7 @@ def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=
     have = acc is not None
     a = _f64(acc, (-1, 3)).copy() if have else np.zeros_like(pos)
     pot = np.zeros(pos.shape[0])
-    p = params(theta, eps, G, leaf_cap)
+    p = params(theta, eps, G, leaf_cap, quad)
     rc = lib().or_kdk(pos.shape[0], pos, vel, mass, C.byref(p), float(dt), int(nsteps), a, int(have),
                       _ptr(pot), int(nthreads))
     if rc:

@@ -188,12 +188,33 @@ static void upward(or_tree *t)
         for (int d = 0; d < 3; d++) t->com[3 * id + d] = t->com[3 * id + d] / t->M[id];
 }
 
+/* ---- second moments about the centre of mass, from the particles of each node ---- */
+static void second_moments(or_tree *t)
+{
+    t->S2 = (double *)malloc(sizeof(double) * 6 * (t->nn > 0 ? t->nn : 1));
+    for (int64_t id = 0; id < t->nn; id++) {
+        const double *c = &t->com[3 * id];
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t r = t->first[id]; r < t->first[id] + t->count[id]; r++) {
+            double m = t->smass[r];
+            double x = t->spos[3 * r] - c[0], y = t->spos[3 * r + 1] - c[1], z = t->spos[3 * r + 2] - c[2];
+            S[0] = S[0] + m * x * x;
+            S[1] = S[1] + m * y * y;
+            S[2] = S[2] + m * z * z;
+            S[3] = S[3] + m * x * y;
+            S[4] = S[4] + m * x * z;
+            S[5] = S[5] + m * y * z;
+        }
+        memcpy(&t->S2[6 * id], S, sizeof(S));
+    }
+}
+
 void or_tree_destroy(or_tree *t)
 {
     if (!t) return;
     free(t->keys); free(t->perm); free(t->spos); free(t->smass);
     free(t->level); free(t->parent); free(t->nchild); free(t->child);
-    free(t->first); free(t->count); free(t->M); free(t->com);
+    free(t->first); free(t->count); free(t->M); free(t->com); free(t->S2);
     free(t);
 }
 
@@ -233,7 +254,13 @@ or_tree *or_tree_create(int64_t n, const double *pos, const double *mass, int32_
     build_rec(&b, 0, 0, (uint32_t)n, -1);
     if (b.failed) { or_tree_destroy(t); return NULL; }
     upward(t);
+    second_moments(t);
     return t;
+}
+
+void or_tree_moments(const or_tree *t, double *S6)
+{
+    memcpy(S6, t->S2, sizeof(double) * 6 * t->nn);
 }
 
 int64_t or_tree_nn(const or_tree *t) { return t->nn; }
@@ -270,6 +297,33 @@ static void interact(const double x[3], const double y[3], double m, double eps2
     *phi = *phi - G * m * rinv;
 }
 
+/* ---- quadrupole term of a cube (mass distribution with second moments S about its
+ *      centre c) on body x, from the second-order expansion of the same softened
+ *      potential:  phi = -G [M / s + A / (2 s^5)],  with d = c - x,  s^2 = |d|^2 + eps^2,
+ *      A = 3 d.S.d - s^2 tr S; the acceleration is minus its gradient in x,
+ *      a = G [M d / s^3 + 5 A d / (2 s^7) - (3 S.d - tr S d) / s^5].
+ *      This adds the second-order part only (the monopole is interact()). ---- */
+static void interact_quad(const double x[3], const double c[3], const double S[6], double eps2, double G,
+                          double a[3], double *phi)
+{
+    double d[3];
+    for (int k = 0; k < 3; k++) d[k] = c[k] - x[k];
+    double s2 = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) + eps2;
+    if (s2 == 0.0) return;
+    double Sd[3];
+    Sd[0] = (S[0] * d[0] + S[3] * d[1]) + S[4] * d[2];
+    Sd[1] = (S[3] * d[0] + S[1] * d[1]) + S[5] * d[2];
+    Sd[2] = (S[4] * d[0] + S[5] * d[1]) + S[2] * d[2];
+    double dSd = (d[0] * Sd[0] + d[1] * Sd[1]) + d[2] * Sd[2];
+    double tr = (S[0] + S[1]) + S[2];
+    double A = 3.0 * dSd - s2 * tr;
+    double s = sqrt(s2);
+    double inv5 = 1.0 / (s2 * s2 * s);
+    double inv7 = inv5 / s2;
+    for (int k = 0; k < 3; k++) a[k] = a[k] + G * (2.5 * A * inv7 * d[k] - inv5 * (3.0 * Sd[k] - tr * d[k]));
+    *phi = *phi - G * 0.5 * A * inv5;
+}
+
 #define WALK_STACK 256
 
 /* ---- the walk for one body (original index i, position x) ---- */
@@ -293,6 +347,7 @@ static void walk_one(const or_tree *t, int64_t i, const double x[3], const or_pa
         double s = ldexp(L, -t->level[id]);
         if (s * s < theta2 * D2) {
             interact(x, c, t->M[id], eps2, p->G, a, phi);
+            if (p->quad) interact_quad(x, c, &t->S2[6 * id], eps2, p->G, a, phi);
             (*nm)++;
             *h += or_mix64((uint64_t)id);
         } else if (t->nchild[id] == 0) {

@@ -36,6 +36,7 @@ extern "C" {
 typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;
+    int32_t quad;           /* 1: accepted cubes add their quadrupole term (see or_tree_moments) */
 } or_params;
 
 typedef struct {
@@ -49,6 +50,7 @@ typedef struct {
     int32_t *level, *parent, *nchild, *child; /* child: nn x 8, -1 padded */
     uint32_t *first, *count;
     double *M, *com;        /* node mass and centre of mass (nn x 3) */
+    double *S2;             /* second moment about the centre of mass (nn x 6: xx yy zz xy xz yz) */
 } or_tree;
 
 /* root cube (c-1) and keys (c-2) */
@@ -65,6 +67,12 @@ int64_t or_tree_nn(const or_tree *t);
 void or_tree_export(const or_tree *t, double lo[3], int32_t *k, uint64_t *keys, uint32_t *perm,
                     int32_t *level, uint32_t *first, uint32_t *count, int32_t *parent,
                     int32_t *nchild, double *M, double *com);
+
+/* Second moments about each node's centre of mass, by their definition
+ * S_ab = sum over the node's particles of m (x_a - c_a)(x_b - c_b), summed in rank
+ * order (nn x 6: xx yy zz xy xz yz).  They carry the quadrupole of the cube's mass
+ * distribution: the paper names multipole moments as future work (section 6). */
+void or_tree_moments(const or_tree *t, double *S6);
 
 /* walk for the given targets (original indices; NULL = all n in index order).
  * Outputs are indexed by target slot.  Any output may be NULL. */
