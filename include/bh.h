@@ -68,9 +68,18 @@ typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
  *            opening decisions are certified against the FP64 test (re-evaluated in
  *            FP64 when the FP32 value is within its rounding bound of the threshold),
  *            so the interaction sets are those of the FP64 method.
- *  flags     0, or for server requests BH_REQ_RELEASE: free the request's state when it
- *            completes (its energies stay available; bh_server_fetch is then refused). */
+ *  flags     bit set of
+ *            BH_QUADRUPOLE: an accepted cube adds its quadrupole term, the second-order
+ *              term of the same softened potential about its centre of mass (second
+ *              moments S about the centre; with d = com - x, s^2 = |d|^2 + eps^2,
+ *              A = 3 d.S.d - s^2 tr S: phi += -G A / (2 s^5), a += G [5 A d / (2 s^7)
+ *              - (3 S.d - tr S d) / s^5]).  The paper names multipole moments as future
+ *              work (section 6).  Interaction sets are unchanged.
+ *            BH_REQ_RELEASE (server requests only): free the request's state when it
+ *              completes (its energies stay available; bh_server_fetch is then refused).
+ *            Other bits are rejected (BH_E_INVAL). */
 #define BH_REQ_RELEASE 1u
+#define BH_QUADRUPOLE 2u
 typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;

@@ -31,9 +31,12 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
-def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64") -> Params:
+QUADRUPOLE = 2
+
+
+def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False) -> Params:
     prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
-    return Params(float(theta), float(eps), float(G), int(leaf_cap), prec, 0, 0)
+    return Params(float(theta), float(eps), float(G), int(leaf_cap), prec, QUADRUPOLE if quad else 0, 0)
 
 
 class Stats(C.Structure):

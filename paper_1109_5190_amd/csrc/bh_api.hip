@@ -35,6 +35,7 @@ bh_status bh_check_params(const bh_params *p) {
     if (!std::isfinite(p->G)) return bh_fail(BH_E_INVAL, "G must be finite");
     if (p->leaf_cap < 1 || p->leaf_cap > 64) return bh_fail(BH_E_INVAL, "leaf_cap must be in [1, 64]");
     if (p->precision != BH_FP64 && p->precision != BH_FP32) return bh_fail(BH_E_INVAL, "precision must be BH_FP64 or BH_FP32");
+    if (p->flags & ~(uint32_t)(BH_QUADRUPOLE | BH_REQ_RELEASE)) return bh_fail(BH_E_INVAL, "unknown bits in flags");
     return BH_OK;
 }
 
@@ -63,7 +64,7 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
     F.tiles.clear();
     F.groups.clear();
     uint64_t ntot = 0;
-    bool has32 = false, has64 = false;
+    uint32_t has32 = 0, has64 = 0;
     for (int32_t s = 0; s < nseg; ++s) {
         SegDesc &d = F.seg[s];
         d.start = (uint32_t)ntot;
@@ -78,7 +79,8 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.eps = p[s].eps;
         d.G = p[s].G;
         d.dt = 0.0;
-        (p[s].precision == BH_FP32 ? has32 : has64) = true;
+        d.quad = (p[s].flags & BH_QUADRUPOLE) ? 1u : 0u;
+        (p[s].precision == BH_FP32 ? has32 : has64) |= d.quad ? 2u : 1u;
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;
             uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);
@@ -110,6 +112,7 @@ ForestCaps bh_caps_of(const ForestHost &F) {
     c.ngroups = F.dev.ngroups;
     c.fp32 = F.dev.has32 != 0;
     c.fp64 = F.dev.has64 != 0;
+    c.quad = ((F.dev.has32 | F.dev.has64) & 2u) != 0;
     return c;
 }
 
@@ -156,6 +159,9 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.nS = c.take<double>(3 * Mc);
     D.w32 = cap.fp32 ? c.take<WRec32>(Mc) : nullptr;
     D.w64 = cap.fp64 ? c.take<WRec64>(Mc) : nullptr;
+    D.uQ = cap.quad ? c.take<double>(6 * (size_t)Mc) : nullptr;
+    D.q32 = cap.quad && cap.fp32 ? c.take<float4>(2 * (size_t)Mc) : nullptr;
+    D.q64 = cap.quad && cap.fp64 ? c.take<double>(6 * (size_t)Mc) : nullptr;
     D.err = c.take<uint32_t>(64);
     D.stats = c.take<unsigned long long>(8);
     D.red = c.take<double>(2 * S);
@@ -190,7 +196,7 @@ bh_status bh_forest_upload_tables(ForestHost &F) {
     ForestDev &D = F.dev;
     const ForestCaps &c = F.caps;
     if (D.nseg > c.nseg || D.ntot > c.ntot || D.ntiles > c.ntiles || D.ngroups > c.ngroups ||
-        (D.has32 && !c.fp32) || (D.has64 && !c.fp64))
+        (D.has32 && !c.fp32) || (D.has64 && !c.fp64) || (((D.has32 | D.has64) & 2u) && !c.quad))
         return bh_fail(BH_E_NOMEM, "forest membership exceeds the planned capacity");
     HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
     if (!F.tiles.empty())

@@ -648,7 +648,8 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
             if (nc != 0) {
                 lvl = f.nlevel[g];
                 rank = atomicAdd(&hist[lvl], 1u);
-                entry = make_uint4(sl, f.nseg + f.cs[g], nc, 0u);
+                const uint32_t quad = f.uQ ? f.seg[f.segid[f.nfirst[g]]].quad : 0u;
+                entry = make_uint4(sl, f.nseg + f.cs[g], nc, quad);
             }
         }
     }
@@ -738,6 +739,23 @@ __global__ void k_up_leaf(ForestDev f) {
     f.uS[3 * (size_t)sl] = Sx;
     f.uS[3 * (size_t)sl + 1] = Sy;
     f.uS[3 * (size_t)sl + 2] = Sz;
+    if (f.uQ && f.seg[f.segid[a]].quad) {
+        // second moments about the leaf's centre of mass, from its particles in key order
+        const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+        double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (uint32_t r = a; r < b; ++r) {
+            const double m = f.smass[r];
+            const double x = f.spos[3 * (size_t)r] - cx, y = f.spos[3 * (size_t)r + 1] - cy,
+                         z = f.spos[3 * (size_t)r + 2] - cz;
+            q[0] += m * x * x;
+            q[1] += m * y * y;
+            q[2] += m * z * z;
+            q[3] += m * x * y;
+            q[4] += m * x * z;
+            q[5] += m * y * z;
+        }
+        for (int k = 0; k < 6; ++k) f.uQ[6 * (size_t)sl + k] = q[k];
+    }
 }
 
 // One wavefront per block of 256 node ids: its level-`level` internal nodes,
@@ -764,6 +782,26 @@ __global__ void __launch_bounds__(256) k_up_level(ForestDev f, int level, uint32
             f.uS[3 * (size_t)sl] = Sx;
             f.uS[3 * (size_t)sl + 1] = Sy;
             f.uS[3 * (size_t)sl + 2] = Sz;
+            if (e.w) {
+                // second moments by the parallel-axis rule: each child's moments about its own
+                // centre plus its mass times the offset of that centre from this node's
+                const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+                double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (uint32_t k = 0; k < nc; ++k) {
+                    const size_t c = c0 + k;
+                    const double mc = f.uM[c];
+                    const double x = f.uS[3 * c] / mc - cx, y = f.uS[3 * c + 1] / mc - cy,
+                                 z = f.uS[3 * c + 2] / mc - cz;
+                    const double *qc = f.uQ + 6 * c;
+                    q[0] += qc[0] + mc * x * x;
+                    q[1] += qc[1] + mc * y * y;
+                    q[2] += qc[2] + mc * z * z;
+                    q[3] += qc[3] + mc * x * y;
+                    q[4] += qc[4] + mc * x * z;
+                    q[5] += qc[5] + mc * y * z;
+                }
+                for (int k = 0; k < 6; ++k) f.uQ[6 * (size_t)sl + k] = q[k];
+            }
         }
     }
 }
@@ -833,6 +871,11 @@ __global__ void k_records(ForestDev f) {
         w.level = (uint32_t)level;
         w.pad[0] = w.pad[1] = 0;
         f.w32[sl] = w;
+        if (sd.quad) {
+            const double *q = f.uQ + 6 * (size_t)sl;
+            f.q32[2 * (size_t)sl] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
+            f.q32[2 * (size_t)sl + 1] = make_float4((float)q[4], (float)q[5], (float)(q[0] + q[1] + q[2]), 0.0f);
+        }
     } else {
         WRec64 w;
         w.x = c[0];
@@ -846,6 +889,8 @@ __global__ void k_records(ForestDev f) {
         w.level = (uint32_t)level;
         w.pad = 0.0;
         f.w64[sl] = w;
+        if (sd.quad)
+            for (int k = 0; k < 6; ++k) f.q64[6 * (size_t)sl + k] = f.uQ[6 * (size_t)sl + k];
     }
 }
 

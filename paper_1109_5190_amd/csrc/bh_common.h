@@ -33,7 +33,7 @@ struct SegDesc {
     const double *pos, *mass;
     double *vel, *acc, *pot;
     uint32_t phase;             // kPhase* bits: which parts of a step apply this iteration
-    uint32_t pad;
+    uint32_t quad;              // 1: accepted cubes add their quadrupole term
 };
 
 constexpr uint32_t kPhaseDrift = 1u, kPhaseKick2 = 2u, kPhaseKick1 = 4u;
@@ -80,7 +80,7 @@ struct WRec64 {
 // Device-side views of one forest's buffers (all sub-allocated from the caller's workspace).
 struct ForestDev {
     uint32_t nseg, ntot, ntiles, ngroups, mcap;   // current membership (mcap = 2 ntot)
-    uint32_t has32, has64;                        // precisions present
+    uint32_t has32, has64;                        // per precision: bit 0 monopole, bit 1 quadrupole simulations
     SegDesc *seg;
     SegState *st;
     TileDesc *tiles;
@@ -101,9 +101,12 @@ struct ForestDev {
     uint32_t *cs;               // exclusive scan of nchild
     uint32_t *slot_of;          // walk slot of each node
     uint4 *lvl_list;            // per block of 256 node ids: its internal nodes sorted by level,
-                                //   as (slot, first child slot, children, 0)
+                                //   as (slot, first child slot, children, quadrupole flag)
     uint16_t *blk_lvl;          // per such block: start of each level in its list (23 entries)
     double *uM, *uS;            // upward pass: mass and mass-weighted position sums by walk slot
+    double *uQ;                 // upward pass: second moments about the centre of mass by slot (6), quadrupole forests
+    float4 *q32;                // FP32 walk: second moments by slot, (xx yy zz xy) (xz yz tr 0)
+    double *q64;                // FP64 walk: second moments by slot (xx yy zz xy xz yz)
     uint8_t *rlam;              // per row that starts a leaf: the leaf's level
     unsigned long long *tile_mm; // per tile: integer images of the bbox min (3) and max (3)
     double *nM, *nS;            // node mass, centre of mass (FP64; S then com in place)

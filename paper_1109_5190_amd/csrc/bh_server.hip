@@ -301,6 +301,7 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     cap.ntiles = (uint32_t)(max_resident_particles / kTile + max_slots + 1);
     cap.ngroups = (uint32_t)(max_resident_particles / kGroup + max_slots + 1);
     cap.fp32 = cap.fp64 = true;
+    cap.quad = true;
     size_t ws = bh_forest_carve(sv->F, cap, nullptr);
     size_t scratch_bytes = align256(sizeof(double) * (6 * 256 + 8));
     if (ws + scratch_bytes >= arena_bytes) {

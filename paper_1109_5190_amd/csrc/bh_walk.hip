@@ -81,9 +81,13 @@ struct WaveLds32 {
     float2 sb[8];          // child: accept above hi, decide in FP64 at or above lo (this wavefront)
     uint2 sl[8];           // child: link, cnt
     uint2 sc[8];           // child: gid, level
+    float4 sq0[8], sq1[8]; // child (quadrupole walks): second moments (xx yy zz xy) (xz yz tr 0)
     uint32_t irank[64];    // queued leaf particles: rank
     uint64_t imask[64];    //                        lane mask
-    float4 pst[64];        //                        position rel g, mass
+    union {
+        float4 pst[64];    //                        position rel g, mass
+        double4 pdt[32];   //                        or FP64 position, mass (unsoftened walks)
+    };
 };
 
 // ------------------------------------------------------------- FP32 walk ---
@@ -104,7 +108,7 @@ struct WaveLds32 {
 // repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
 // into FP32 partial sums that are folded into Kahan-compensated totals after
 // at most 64 terms.
-template <bool STATS, bool POT, int W>
+template <bool STATS, bool POT, int W, bool QUAD>
 __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     __shared__ WaveLds32 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 1) return;
+    if (sd.precision != 1 || (sd.quad != 0) != QUAD) return;
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
@@ -166,6 +170,45 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         if (qn == 0) return;
         if (work + qn > kFlushWork) fold();
         work += qn;
+        if (!soft) {
+            // without softening a pair can be far closer than the group's extent: its
+            // difference is formed in FP64 and rounded once, so it carries u |d|, not u |x - g|
+            const double xi = f.spos[3 * (size_t)r], yi = f.spos[3 * (size_t)r + 1], zi = f.spos[3 * (size_t)r + 2];
+            for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+                const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    const size_t j = L.irank[k0 + lane];
+                    L.pdt[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+                }
+                wave_sync();
+                for (uint32_t k = 0; k < nb; ++k) {
+                    const uint32_t jq = uni(L.irank[k0 + k]);
+                    const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                    if (in_mask(m)) {
+                        const double4 p = L.pdt[k];
+                        const float dx = (float)(p.x - xi), dy = (float)(p.y - yi), dz = (float)(p.z - zi);
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (r2 > 0.0f) {
+                            const float ri = __builtin_amdgcn_rsqf(r2);
+                            const float mr = (float)p.w * ri;
+                            const float w3 = mr * ri * ri;
+                            ax = fmaf(w3, dx, ax);
+                            ay = fmaf(w3, dy, ay);
+                            az = fmaf(w3, dz, az);
+                            if (POT) ap -= mr;
+                        }
+                        if (STATS) {
+                            ++np2p;
+                            h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                        }
+                    }
+                }
+            }
+            qn = 0;
+            wave_sync();
+            return;
+        }
         wave_sync();
         if ((uint32_t)lane < qn) {
             const size_t j = L.irank[lane];
@@ -211,6 +254,10 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
             L.sb[lane] = make_float2((w.Sp + B) * (1.0f + 4.0f * kU32), fmaxf(w.Sp - B, 0.0f) * (1.0f - 4.0f * kU32));
             L.sl[lane] = make_uint2(w.link, w.cnt);
             L.sc[lane] = make_uint2(w.gid, w.level);
+            if (QUAD) {
+                L.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
+                L.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
+            }
         }
         wave_sync();
         if (work + nch > kFlushWork) fold();
@@ -288,7 +335,49 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                 __asm__ volatile("");
                 const float ri = __builtin_amdgcn_rsqf(E2);
                 const float mr = qa.w * ri;
-                const float w3 = mr * ri * ri;
+                const float ri2 = ri * ri;
+                float w3 = mr * ri2;
+                if (QUAD) {
+                    // + G [5 A d / (2 s^7) - (3 S.d - tr S d) / s^5],  A = 3 d.S.d - s^2 tr S
+                    const float4 s0 = L.sq0[c], s1 = L.sq1[c];
+                    const float sdx = fmaf(s0.x, dx, fmaf(s0.w, dy, s1.x * dz));
+                    const float sdy = fmaf(s0.w, dx, fmaf(s0.y, dy, s1.y * dz));
+                    const float sdz = fmaf(s1.x, dx, fmaf(s1.y, dy, s0.z * dz));
+                    const float A = fmaf(3.0f, fmaf(dx, sdx, fmaf(dy, sdy, dz * sdz)), -E2 * s1.z);
+                    const float ri5 = ri2 * ri2 * ri;
+                    float qx = -ri5 * fmaf(3.0f, sdx, -s1.z * dx) + 2.5f * A * ri5 * ri2 * dx;
+                    float qy = -ri5 * fmaf(3.0f, sdy, -s1.z * dy) + 2.5f * A * ri5 * ri2 * dy;
+                    float qz = -ri5 * fmaf(3.0f, sdz, -s1.z * dz) + 2.5f * A * ri5 * ri2 * dz;
+                    float qp = -0.5f * A * ri5;
+                    // tr S > M s^2: the body is close to (or inside) the cube, the terms of the
+                    // expansion nearly cancel and FP32 loses them; those lanes take it in FP64
+                    const uint64_t hard = ballot(s1.z > qa.w * E2) & accm;
+                    if (hard) {
+                        if (in_mask(hard)) {
+                            const uint2 qc = L.sc[c];
+                            const double *cm = f.nS + 3 * (size_t)qc.x;
+                            const double *xp = f.spos + 3 * (size_t)r;
+                            const double *S = f.uQ + 6 * (size_t)(link + c);
+                            const double ex_ = cm[0] - xp[0], ey = cm[1] - xp[1], ez = cm[2] - xp[2];
+                            const double e2 = ((ex_ * ex_ + ey * ey) + ez * ez) + (double)sd.eps * sd.eps;
+                            const double tr = (S[0] + S[1]) + S[2];
+                            const double sx = fma(S[0], ex_, fma(S[3], ey, S[4] * ez));
+                            const double sy = fma(S[3], ex_, fma(S[1], ey, S[5] * ez));
+                            const double sz = fma(S[4], ex_, fma(S[5], ey, S[2] * ez));
+                            const double A64 = fma(3.0, fma(ex_, sx, fma(ey, sy, ez * sz)), -e2 * tr);
+                            const double rinv = 1.0 / sqrt(e2);
+                            const double r5 = rinv * rinv * rinv * rinv * rinv, r7 = r5 * rinv * rinv;
+                            qx = (float)(2.5 * A64 * r7 * ex_ - r5 * fma(3.0, sx, -tr * ex_));
+                            qy = (float)(2.5 * A64 * r7 * ey - r5 * fma(3.0, sy, -tr * ey));
+                            qz = (float)(2.5 * A64 * r7 * ez - r5 * fma(3.0, sz, -tr * ez));
+                            qp = (float)(-0.5 * A64 * r5);
+                        }
+                    }
+                    ax += qx;
+                    ay += qy;
+                    az += qz;
+                    if (POT) ap += qp;
+                }
                 ax = fmaf(w3, dx, ax);
                 ay = fmaf(w3, dy, ay);
                 az = fmaf(w3, dz, az);
@@ -343,12 +432,13 @@ struct WaveLds64 {
     double4 sa[8];         // child: centre of mass, mass
     double sS[8];          // child: side^2
     uint4 sb[8];           // child: link, cnt, gid, level
+    double sq[8 * 6];      // child (quadrupole walks): second moments (xx yy zz xy xz yz)
     uint32_t irank[64];
     uint64_t imask[64];
     double4 pst[64];
 };
 
-template <bool STATS, bool POT, int W>
+template <bool STATS, bool POT, int W, bool QUAD>
 __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     __shared__ WaveLds64 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -359,7 +449,7 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 0) return;
+    if (sd.precision != 0 || (sd.quad != 0) != QUAD) return;
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
@@ -426,6 +516,8 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
             L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
             L.sS[lane] = w.S;
             L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
+            if (QUAD)
+                for (int k = 0; k < 6; ++k) L.sq[6 * lane + k] = f.q64[6 * (size_t)(link + lane) + k];
         }
         wave_sync();
 #pragma unroll
@@ -473,9 +565,25 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
             if (in_mask(accm)) {
                 // softened monopole, executed by the accepting lanes only
                 __asm__ volatile("");
-                const double ri = rsqrt64(D2 + eps2);
+                const double E2 = D2 + eps2;
+                const double ri = rsqrt64(E2);
                 const double mr = qa.w * ri;
-                const double w3 = mr * ri * ri;
+                const double ri2 = ri * ri;
+                double w3 = mr * ri2;
+                if (QUAD) {
+                    const double *q = &L.sq[6 * c];
+                    const double sdx = fma(q[0], dx, fma(q[3], dy, q[4] * dz));
+                    const double sdy = fma(q[3], dx, fma(q[1], dy, q[5] * dz));
+                    const double sdz = fma(q[4], dx, fma(q[5], dy, q[2] * dz));
+                    const double tr = (q[0] + q[1]) + q[2];
+                    const double A = fma(3.0, fma(dx, sdx, fma(dy, sdy, dz * sdz)), -E2 * tr);
+                    const double ri5 = ri2 * ri2 * ri;
+                    w3 = fma(2.5 * A, ri5 * ri2, w3);
+                    ax = fma(-ri5, fma(3.0, sdx, -tr * dx), ax);
+                    ay = fma(-ri5, fma(3.0, sdy, -tr * dy), ay);
+                    az = fma(-ri5, fma(3.0, sdz, -tr * dz), az);
+                    if (POT) ap -= 0.5 * A * ri5;
+                }
                 ax = fma(w3, dx, ax);
                 ay = fma(w3, dy, ay);
                 az = fma(w3, dz, az);
@@ -517,42 +625,40 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     }
 }
 
-// One walk launch: W wavefronts (one group each) per block.  The launch shape
-// does not change any result (each group's arithmetic is its own); forests
-// pick it by measurement (bh_forest_autotune).
-template <int W>
-static void launch_walk_w(const ForestDev &f, bool stats, bool want_pot, const WalkOut &o, hipStream_t s) {
+// Walk launches: W wavefronts (one 64-body group each) per workgroup, one kernel
+// per precision and expansion order present.  The launch shape does not change
+// any result (each group's arithmetic is its own); forests pick it by
+// measurement (bh_forest_autotune).
+template <bool STATS, bool POT, int W>
+static void launch_walk_sp(const ForestDev &f, const WalkOut &o, hipStream_t s) {
     const unsigned blocks = (f.ngroups + W - 1) / W;
     const dim3 g(blocks), b(64 * W);
-    if (f.has32) {
-        if (stats) {
-            if (want_pot) hipLaunchKernelGGL((k_walk32<true, true, W>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<true, false, W>), g, b, 0, s, f, o);
-        } else {
-            if (want_pot) hipLaunchKernelGGL((k_walk32<false, true, W>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk32<false, false, W>), g, b, 0, s, f, o);
-        }
-    }
-    if (f.has64) {
-        if (stats) {
-            if (want_pot) hipLaunchKernelGGL((k_walk64<true, true, W>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<true, false, W>), g, b, 0, s, f, o);
-        } else {
-            if (want_pot) hipLaunchKernelGGL((k_walk64<false, true, W>), g, b, 0, s, f, o);
-            else hipLaunchKernelGGL((k_walk64<false, false, W>), g, b, 0, s, f, o);
-        }
-    }
+    if (f.has32 & 1u) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false>), g, b, 0, s, f, o);
+    if (f.has32 & 2u) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true>), g, b, 0, s, f, o);
+    if (f.has64 & 1u) hipLaunchKernelGGL((k_walk64<STATS, POT, W, false>), g, b, 0, s, f, o);
+    if (f.has64 & 2u) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true>), g, b, 0, s, f, o);
+}
+
+template <int W>
+static void launch_walk_w(const ForestDev &f, bool want_pot, const WalkOut &o, hipStream_t s) {
+    if (want_pot) launch_walk_sp<false, true, W>(f, o, s);
+    else launch_walk_sp<false, false, W>(f, o, s);
 }
 
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves) {
     WalkOut o{acc, pot, n_mono, n_p2p, hash};
     if (f.ngroups == 0) return hipSuccess;
+    if (stats) {   // the counting walks use one launch shape
+        if (want_pot) launch_walk_sp<true, true, 4>(f, o, s);
+        else launch_walk_sp<true, false, 4>(f, o, s);
+        return hipGetLastError();
+    }
     switch (waves) {
-        case 1: launch_walk_w<1>(f, stats, want_pot, o, s); break;
-        case 2: launch_walk_w<2>(f, stats, want_pot, o, s); break;
-        case 8: launch_walk_w<8>(f, stats, want_pot, o, s); break;
-        default: launch_walk_w<4>(f, stats, want_pot, o, s); break;
+        case 1: launch_walk_w<1>(f, want_pot, o, s); break;
+        case 2: launch_walk_w<2>(f, want_pot, o, s); break;
+        case 8: launch_walk_w<8>(f, want_pot, o, s); break;
+        default: launch_walk_w<4>(f, want_pot, o, s); break;
     }
     return hipGetLastError();
 }

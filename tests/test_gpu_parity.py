@@ -84,6 +84,7 @@ WALK_CASES = [
     ("plummer", 4096, 1, 0.5, 0.01, 16),
     ("plummer", 4096, 1, 0.3, 0.01, 1),
     ("plummer", 4096, 1, 0.7, 0.01, 1),
+    ("plummer", 20000, 4, 1.0, 0.0, 1),   # unsoftened: close pairs dominate the error norm
     ("plummer", 4096, 1, 1.0, 0.01, 1),
     ("uniform", 20001, 5, 0.5, 0.005, 1),
     ("two_spheres", 20000, 3, 0.5, 0.005, 4),
