@@ -60,6 +60,8 @@ def lib():
         L.or_tree_nn.argtypes = [C.c_void_p]
         L.or_tree_nn.restype = C.c_int64
         L.or_tree_moments.argtypes = [C.c_void_p, _f64p]
+        L.or_tree_walk_group.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.or_tree_export.argtypes = [C.c_void_p, _f64p, C.POINTER(C.c_int32), _u64p, _u32p, _i32p,
                                      _u32p, _u32p, _i32p, _i32p, _f64p, _f64p]
         opt = lambda t: C.c_void_p  # noqa: E731  (nullable array arguments)
@@ -169,6 +171,22 @@ class Tree:
                                 _ptr(nm), _ptr(np_), _ptr(hs), int(nthreads))
         if rc:
             raise ValueError("oracle walk rejected its arguments")
+        return dict(acc=acc, pot=pot, n_mono=nm, n_p2p=np_, hash=hs)
+
+    def walk_group(self, theta=0.5, eps=0.01, G=1.0, group=64, targets=None, nthreads=0):
+        """Group-criterion variant: one interaction list per `group` key-consecutive bodies."""
+        p = params(theta, eps, G, 1)
+        t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+        nt = self.n if t is None else t.shape[0]
+        acc = np.zeros((nt, 3))
+        pot = np.zeros(nt)
+        nm = np.zeros(nt, np.int64)
+        np_ = np.zeros(nt, np.int64)
+        hs = np.zeros(nt, np.uint64)
+        rc = lib().or_tree_walk_group(self._h, C.byref(p), int(group), nt, _ptr(t), _ptr(acc), _ptr(pot),
+                                      _ptr(nm), _ptr(np_), _ptr(hs), int(nthreads))
+        if rc:
+            raise ValueError("oracle group walk rejected its arguments")
         return dict(acc=acc, pot=pot, n_mono=nm, n_p2p=np_, hash=hs)
 
     def __del__(self):

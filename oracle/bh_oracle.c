@@ -392,6 +392,109 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
     return 0;
 }
 
+/* ---- group-criterion walk: one interaction list per group of key-consecutive bodies ---- */
+typedef struct { int32_t *id; int64_t n, cap; } id_list;
+
+static void list_push(id_list *l, int32_t v)
+{
+    if (l->n == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 256;
+        l->id = (int32_t *)realloc(l->id, sizeof(int32_t) * l->cap);
+    }
+    l->id[l->n++] = v;
+}
+
+int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int64_t ntarget,
+                       const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
+                       int64_t *n_p2p, uint64_t *hash, int nthreads)
+{
+    if (!t || !p || group < 1 || !(p->theta >= 0.0) || !(p->eps >= 0.0)) return 1;
+    const int64_t n = t->n;
+    double *A = (double *)malloc(sizeof(double) * 3 * n), *P = (double *)malloc(sizeof(double) * n);
+    int64_t *NM = (int64_t *)malloc(sizeof(int64_t) * n), *NP = (int64_t *)malloc(sizeof(int64_t) * n);
+    uint64_t *H = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    const double theta2 = p->theta * p->theta, eps2 = p->eps * p->eps, L = ldexp(1.0, t->k);
+    const int64_t ngroups = (n + group - 1) / group;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t g = 0; g < ngroups; g++) {
+        const int64_t r0 = g * group, r1 = r0 + group < n ? r0 + group : n;
+        double lo[3], hi[3];
+        for (int k = 0; k < 3; k++) lo[k] = hi[k] = t->spos[3 * r0 + k];
+        for (int64_t r = r0 + 1; r < r1; r++)
+            for (int k = 0; k < 3; k++) {
+                double v = t->spos[3 * r + k];
+                if (v < lo[k]) lo[k] = v;
+                if (v > hi[k]) hi[k] = v;
+            }
+        /* the group's list, in depth-first order */
+        id_list mono = {0, 0, 0}, leaves = {0, 0, 0};
+        int32_t stack[WALK_STACK];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            int32_t id = stack[--sp];
+            const double *c = &t->com[3 * id];
+            double dd[3];
+            for (int k = 0; k < 3; k++) {
+                double u = lo[k] - c[k], v = c[k] - hi[k];
+                double w = u > v ? u : v;
+                dd[k] = w > 0.0 ? w : 0.0;
+            }
+            double D2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+            double s = ldexp(L, -t->level[id]);
+            if (s * s < theta2 * D2) list_push(&mono, id);
+            else if (t->nchild[id] == 0) list_push(&leaves, id);
+            else for (int cc = t->nchild[id] - 1; cc >= 0; cc--) stack[sp++] = t->child[8 * id + cc];
+        }
+        for (int64_t r = r0; r < r1; r++) {
+            const int64_t i = t->perm[r];
+            const double *x = &t->spos[3 * r];
+            double a[3] = {0.0, 0.0, 0.0}, phi = 0.0;
+            int64_t nm = 0, np = 0;
+            uint64_t h = 0;
+            for (int64_t q = 0; q < mono.n; q++) {
+                int32_t id = mono.id[q];
+                interact(x, &t->com[3 * id], t->M[id], eps2, p->G, a, &phi);
+                nm++;
+                h += or_mix64((uint64_t)id);
+            }
+            for (int64_t q = 0; q < leaves.n; q++) {
+                int32_t id = leaves.id[q];
+                for (uint32_t rr = t->first[id]; rr < t->first[id] + t->count[id]; rr++) {
+                    uint32_t j = t->perm[rr];
+                    if ((int64_t)j == i) continue;
+                    interact(x, &t->spos[3 * rr], t->smass[rr], eps2, p->G, a, &phi);
+                    np++;
+                    h += or_mix64((uint64_t)t->nn + j);
+                }
+            }
+            for (int k = 0; k < 3; k++) A[3 * i + k] = a[k];
+            P[i] = phi;
+            NM[i] = nm;
+            NP[i] = np;
+            H[i] = h;
+        }
+        free(mono.id);
+        free(leaves.id);
+    }
+    if (!targets) ntarget = n;
+    for (int64_t s = 0; s < ntarget; s++) {
+        int64_t i = targets ? targets[s] : s;
+        if (acc) for (int k = 0; k < 3; k++) acc[3 * s + k] = A[3 * i + k];
+        if (pot) pot[s] = P[i];
+        if (n_mono) n_mono[s] = NM[i];
+        if (n_p2p) n_p2p[s] = NP[i];
+        if (hash) hash[s] = H[i];
+    }
+    free(A); free(P); free(NM); free(NP); free(H);
+    return 0;
+}
+
 int or_forces(int64_t n, const double *pos, const double *mass, const or_params *p,
               int64_t ntarget, const int64_t *targets, double *acc, double *pot,
               int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, int nthreads)

@@ -80,6 +80,17 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
                  const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
                  int64_t *n_p2p, uint64_t *hash, int nthreads);
 
+/* Group-criterion walk (a variant, not the paper's per-body test): the bodies in
+ * key order are split into consecutive groups of `group` (the last one shorter);
+ * a cube is accepted for a whole group iff side^2 < theta^2 D^2 with D the distance
+ * from the cube's centre of mass to the group's bounding box (0 inside it), in
+ * FP64 as ((dx*dx + dy*dy) + dz*dz) with dk = max(0, lo_k - c_k, c_k - hi_k).
+ * Every member then takes the same cubes; opened leaves give pairs with every
+ * particle but itself.  With group = 1 this is the per-body walk. */
+int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int64_t ntarget,
+                       const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
+                       int64_t *n_p2p, uint64_t *hash, int nthreads);
+
 /* build + walk in one call */
 int or_forces(int64_t n, const double *pos, const double *mass, const or_params *p,
               int64_t ntarget, const int64_t *targets, double *acc, double *pot,
