@@ -80,7 +80,7 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.G = p[s].G;
         d.dt = 0.0;
         d.quad = (p[s].flags & BH_QUADRUPOLE) ? 1u : 0u;
-        (p[s].precision == BH_FP32 ? has32 : has64) |= d.quad ? 2u : 1u;
+        (p[s].precision == BH_FP32 ? has32 : has64) |= var_bit(d.quad != 0, unsoftened(d.eps));
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;
             uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);
@@ -112,7 +112,7 @@ ForestCaps bh_caps_of(const ForestHost &F) {
     c.ngroups = F.dev.ngroups;
     c.fp32 = F.dev.has32 != 0;
     c.fp64 = F.dev.has64 != 0;
-    c.quad = ((F.dev.has32 | F.dev.has64) & 2u) != 0;
+    c.quad = ((F.dev.has32 | F.dev.has64) & kVarQuadBits) != 0;
     return c;
 }
 
@@ -196,7 +196,7 @@ bh_status bh_forest_upload_tables(ForestHost &F) {
     ForestDev &D = F.dev;
     const ForestCaps &c = F.caps;
     if (D.nseg > c.nseg || D.ntot > c.ntot || D.ntiles > c.ntiles || D.ngroups > c.ngroups ||
-        (D.has32 && !c.fp32) || (D.has64 && !c.fp64) || (((D.has32 | D.has64) & 2u) && !c.quad))
+        (D.has32 && !c.fp32) || (D.has64 && !c.fp64) || (((D.has32 | D.has64) & kVarQuadBits) && !c.quad))
         return bh_fail(BH_E_NOMEM, "forest membership exceeds the planned capacity");
     HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
     if (!F.tiles.empty())

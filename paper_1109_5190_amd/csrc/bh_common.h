@@ -80,7 +80,7 @@ struct WRec64 {
 // Device-side views of one forest's buffers (all sub-allocated from the caller's workspace).
 struct ForestDev {
     uint32_t nseg, ntot, ntiles, ngroups, mcap;   // current membership (mcap = 2 ntot)
-    uint32_t has32, has64;                        // per precision: bit 0 monopole, bit 1 quadrupole simulations
+    uint32_t has32, has64;                        // per precision: walk variants present, var_bit()
     SegDesc *seg;
     SegState *st;
     TileDesc *tiles;
@@ -119,6 +119,17 @@ struct ForestDev {
 };
 
 // ---------------------------------------------------------------- helpers ---
+
+// Walk variant of a simulation: expansion order and whether its FP32 softening is zero
+// (one bit each of ForestDev::has32 / has64; the FP64 walk ignores the softening bit).
+constexpr uint32_t kVarQuad = 1u, kVarUnsoft = 2u;
+__host__ __device__ __forceinline__ uint32_t var_bit(bool quad, bool unsoft) {
+    return 1u << ((quad ? kVarQuad : 0u) | (unsoft ? kVarUnsoft : 0u));
+}
+constexpr uint32_t kVarQuadBits = (1u << kVarQuad) | (1u << (kVarQuad | kVarUnsoft));
+
+// A simulation's FP32 walk is unsoftened when eps^2 rounds to zero in FP32.
+__host__ __device__ __forceinline__ bool unsoftened(double eps) { return !((float)(eps * eps) > 0.0f); }
 
 // Base of a simulation's rows: the concatenated array shifted to its first row,
 // or the simulation's own array.

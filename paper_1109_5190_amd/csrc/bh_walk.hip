@@ -84,10 +84,8 @@ struct WaveLds32 {
     float4 sq0[8], sq1[8]; // child (quadrupole walks): second moments (xx yy zz xy) (xz yz tr 0)
     uint32_t irank[64];    // queued leaf particles: rank
     uint64_t imask[64];    //                        lane mask
-    union {
-        float4 pst[64];    //                        position rel g, mass
-        double4 pdt[32];   //                        or FP64 position, mass (unsoftened walks)
-    };
+    float4 pst[64];        //                        position rel g, mass (unsoftened walks:
+                           //                        32 particles as (hi, mass), (lo, 0))
 };
 
 // ------------------------------------------------------------- FP32 walk ---
@@ -108,7 +106,7 @@ struct WaveLds32 {
 // repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
 // into FP32 partial sums that are folded into Kahan-compensated totals after
 // at most 64 terms.
-template <bool STATS, bool POT, int W, bool QUAD>
+template <bool STATS, bool POT, int W, bool QUAD, bool SOFT>
 __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     __shared__ WaveLds32 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -119,7 +117,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 1 || (sd.quad != 0) != QUAD) return;
+    if (sd.precision != 1 || (sd.quad != 0) != QUAD || unsoftened(sd.eps) == SOFT) return;
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
@@ -135,7 +133,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     const double theta = sd.theta;
     const float eps2 = (float)(sd.eps * sd.eps);
     const float band2 = 16.0f * kU32 * kU32;   // 16 u^2
-    const bool soft = eps2 > 0.0f;
+    constexpr bool soft = SOFT;
 
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
     float sx = 0.f, sy = 0.f, sz = 0.f, sp_ = 0.f;           // Kahan sums
@@ -170,28 +168,37 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         if (qn == 0) return;
         if (work + qn > kFlushWork) fold();
         work += qn;
-        if (!soft) {
-            // without softening a pair can be far closer than the group's extent: its
-            // difference is formed in FP64 and rounded once, so it carries u |d|, not u |x - g|
-            const double xi = f.spos[3 * (size_t)r], yi = f.spos[3 * (size_t)r + 1], zi = f.spos[3 * (size_t)r + 2];
+        if (!SOFT) {
+            // without softening a pair can be far closer than the group's extent: each side
+            // is split as x - g = hi + lo (FP32 pair), so the difference of a close pair,
+            // (hi_j - hi_i) + (lo_j - lo_i), carries u |d| instead of u |x - g|
+            const float tlx = (float)(__dsub_rn(f.spos[3 * (size_t)r], gx) - (double)tx);
+            const float tly = (float)(__dsub_rn(f.spos[3 * (size_t)r + 1], gy) - (double)ty);
+            const float tlz = (float)(__dsub_rn(f.spos[3 * (size_t)r + 2], gz) - (double)tz);
             for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
                 const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
                 wave_sync();
                 if ((uint32_t)lane < nb) {
                     const size_t j = L.irank[k0 + lane];
-                    L.pdt[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+                    const double ex_ = __dsub_rn(f.spos[3 * j], gx), ey = __dsub_rn(f.spos[3 * j + 1], gy),
+                                 ez = __dsub_rn(f.spos[3 * j + 2], gz);
+                    const float hx = (float)ex_, hy = (float)ey, hz = (float)ez;
+                    L.pst[2 * lane] = make_float4(hx, hy, hz, (float)f.smass[j]);
+                    L.pst[2 * lane + 1] = make_float4((float)(ex_ - (double)hx), (float)(ey - (double)hy),
+                                                      (float)(ez - (double)hz), 0.0f);
                 }
                 wave_sync();
                 for (uint32_t k = 0; k < nb; ++k) {
                     const uint32_t jq = uni(L.irank[k0 + k]);
                     const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
                     if (in_mask(m)) {
-                        const double4 p = L.pdt[k];
-                        const float dx = (float)(p.x - xi), dy = (float)(p.y - yi), dz = (float)(p.z - zi);
+                        const float4 ph = L.pst[2 * k], pl = L.pst[2 * k + 1];
+                        const float dx = (ph.x - tx) + (pl.x - tlx), dy = (ph.y - ty) + (pl.y - tly),
+                                    dz = (ph.z - tz) + (pl.z - tlz);
                         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         if (r2 > 0.0f) {
                             const float ri = __builtin_amdgcn_rsqf(r2);
-                            const float mr = (float)p.w * ri;
+                            const float mr = ph.w * ri;
                             const float w3 = mr * ri * ri;
                             ax = fmaf(w3, dx, ax);
                             ay = fmaf(w3, dy, ay);
@@ -633,10 +640,13 @@ template <bool STATS, bool POT, int W>
 static void launch_walk_sp(const ForestDev &f, const WalkOut &o, hipStream_t s) {
     const unsigned blocks = (f.ngroups + W - 1) / W;
     const dim3 g(blocks), b(64 * W);
-    if (f.has32 & 1u) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false>), g, b, 0, s, f, o);
-    if (f.has32 & 2u) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true>), g, b, 0, s, f, o);
-    if (f.has64 & 1u) hipLaunchKernelGGL((k_walk64<STATS, POT, W, false>), g, b, 0, s, f, o);
-    if (f.has64 & 2u) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, false>), g, b, 0, s, f, o);
+    if (f.has64 & (var_bit(false, false) | var_bit(false, true)))
+        hipLaunchKernelGGL((k_walk64<STATS, POT, W, false>), g, b, 0, s, f, o);
+    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true>), g, b, 0, s, f, o);
 }
 
 template <int W>
