@@ -75,11 +75,19 @@ typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
  *              A = 3 d.S.d - s^2 tr S: phi += -G A / (2 s^5), a += G [5 A d / (2 s^7)
  *              - (3 S.d - tr S d) / s^5]).  The paper names multipole moments as future
  *              work (section 6).  Interaction sets are unchanged.
+ *            BH_GROUP_CRITERION: a variant of the opening test (not the paper's): the
+ *              bodies of a walk group (64 key-consecutive bodies) share one decision per
+ *              cube, accepted iff side^2 < theta^2 D^2 with D the distance from the
+ *              cube's centre of mass to the group's bounding box; opened leaves give pairs
+ *              with every particle but the body itself.  More conservative (and more
+ *              accurate) than the per-body test; all lanes of a wavefront take part in
+ *              every cube.  Not combined with BH_QUADRUPOLE.
  *            BH_REQ_RELEASE (server requests only): free the request's state when it
  *              completes (its energies stay available; bh_server_fetch is then refused).
  *            Other bits are rejected (BH_E_INVAL). */
 #define BH_REQ_RELEASE 1u
 #define BH_QUADRUPOLE 2u
+#define BH_GROUP_CRITERION 4u
 typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;

@@ -32,11 +32,13 @@ class Params(C.Structure):
 
 
 QUADRUPOLE = 2
+GROUP_CRITERION = 4
 
 
-def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False) -> Params:
+def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False, group=False) -> Params:
     prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
-    return Params(float(theta), float(eps), float(G), int(leaf_cap), prec, QUADRUPOLE if quad else 0, 0)
+    flags = (QUADRUPOLE if quad else 0) | (GROUP_CRITERION if group else 0)
+    return Params(float(theta), float(eps), float(G), int(leaf_cap), prec, flags, 0)
 
 
 class Stats(C.Structure):

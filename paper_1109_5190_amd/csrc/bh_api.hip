@@ -35,7 +35,10 @@ bh_status bh_check_params(const bh_params *p) {
     if (!std::isfinite(p->G)) return bh_fail(BH_E_INVAL, "G must be finite");
     if (p->leaf_cap < 1 || p->leaf_cap > 64) return bh_fail(BH_E_INVAL, "leaf_cap must be in [1, 64]");
     if (p->precision != BH_FP64 && p->precision != BH_FP32) return bh_fail(BH_E_INVAL, "precision must be BH_FP64 or BH_FP32");
-    if (p->flags & ~(uint32_t)(BH_QUADRUPOLE | BH_REQ_RELEASE)) return bh_fail(BH_E_INVAL, "unknown bits in flags");
+    if (p->flags & ~(uint32_t)(BH_QUADRUPOLE | BH_GROUP_CRITERION | BH_REQ_RELEASE))
+        return bh_fail(BH_E_INVAL, "unknown bits in flags");
+    if ((p->flags & BH_QUADRUPOLE) && (p->flags & BH_GROUP_CRITERION))
+        return bh_fail(BH_E_INVAL, "BH_QUADRUPOLE and BH_GROUP_CRITERION are not combined");
     return BH_OK;
 }
 
@@ -80,7 +83,8 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.G = p[s].G;
         d.dt = 0.0;
         d.quad = (p[s].flags & BH_QUADRUPOLE) ? 1u : 0u;
-        (p[s].precision == BH_FP32 ? has32 : has64) |= var_bit(d.quad != 0, unsoftened(d.eps));
+        d.group = (p[s].flags & BH_GROUP_CRITERION) ? 1u : 0u;
+        (p[s].precision == BH_FP32 ? has32 : has64) |= d.group ? kVarGroup : var_bit(d.quad != 0, unsoftened(d.eps));
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;
             uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);

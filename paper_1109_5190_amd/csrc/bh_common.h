@@ -34,6 +34,8 @@ struct SegDesc {
     double *vel, *acc, *pot;
     uint32_t phase;             // kPhase* bits: which parts of a step apply this iteration
     uint32_t quad;              // 1: accepted cubes add their quadrupole term
+    uint32_t group;             // 1: group criterion (a cube is accepted for the whole walk group)
+    uint32_t pad;
 };
 
 constexpr uint32_t kPhaseDrift = 1u, kPhaseKick2 = 2u, kPhaseKick1 = 4u;
@@ -127,6 +129,7 @@ __host__ __device__ __forceinline__ uint32_t var_bit(bool quad, bool unsoft) {
     return 1u << ((quad ? kVarQuad : 0u) | (unsoft ? kVarUnsoft : 0u));
 }
 constexpr uint32_t kVarQuadBits = (1u << kVarQuad) | (1u << (kVarQuad | kVarUnsoft));
+constexpr uint32_t kVarGroup = 1u << 4;   // group-criterion simulations (their own walk kernels)
 
 // A simulation's FP32 walk is unsoftened when eps^2 rounds to zero in FP32.
 __host__ __device__ __forceinline__ bool unsoftened(double eps) { return !((float)(eps * eps) > 0.0f); }
