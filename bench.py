@@ -111,12 +111,17 @@ def sweep(a, bh, torch):
         tg = np.sort(rng.choice(s.n, min(a.sample, s.n), replace=False)).astype(np.int64)
         tgd = torch.tensor(tg, device=dev)
         exact = oracle.direct(s.pos, s.mass, eps=0.005, targets=tg, nthreads=cores)["acc"]
-        runs = [(th, q) for th in (0.3, 0.5, 0.7, 1.0) for q in (False,)] + [(th, True) for th in (0.5, 0.7, 1.0)]
-        for theta, quad in runs:
-            ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores, quad=quad)
+        runs = ([(th, "monopole") for th in (0.3, 0.5, 0.7, 1.0)] + [(th, "quadrupole") for th in (0.5, 0.7, 1.0)]
+                + [(th, "group") for th in (0.5, 0.7, 1.0)])
+        for theta, variant in runs:
+            quad, group = variant == "quadrupole", variant == "group"
+            if group:
+                ref = T.walk_group(theta, 0.005, 1.0, 64, tg, nthreads=cores)
+            else:
+                ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores, quad=quad)
             inter = None
             for prec in ("fp32", "fp64"):
-                p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec, quad=quad)
+                p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec, quad=quad, group=group)
                 t = bh.Tree(ctx, pos, mass, p).upward()
                 acc = t.forces()
                 if inter is None:
@@ -143,14 +148,14 @@ def sweep(a, bh, torch):
                 rms_exact, _ = _errors(acc[tgd].cpu().numpy(), exact)
                 peak = 157.3e12 if prec == "fp32" else 78.6e12
                 rows.append({"system": name, "n": s.n, "theta": theta, "precision": prec,
-                             "expansion": "quadrupole" if quad else "monopole",
+                             "variant": variant,
                              "rms_rel_vs_direct_sum": rms_exact,
                              "ms_force_eval": ms_eval, "mparticles_per_s": s.n / (ms_eval * 1e-3) / 1e6,
                              "ms_walk": ms_walk, "interactions_per_particle": inter / s.n,
                              "walk_tflops": 20 * inter / (ms_walk * 1e-3) / 1e12,
                              "walk_frac_of_peak": 20 * inter / (ms_walk * 1e-3) / peak,
                              "rms_rel_vs_oracle": rms, "max_rel_vs_oracle": mx})
-                print(f"# {name} theta={theta} {prec}{' quad' if quad else ''}: eval {ms_eval:.3f} ms "
+                print(f"# {name} theta={theta} {prec} {variant}: eval {ms_eval:.3f} ms "
                       f"walk {ms_walk:.3f} ms rms {rms:.2e} max {mx:.2e} vs direct {rms_exact:.2e}",
                       file=sys.stderr, flush=True)
                 del t, t2
@@ -159,7 +164,8 @@ def sweep(a, bh, torch):
             "unit": "Mparticles/s", "n_gpus": 1, "data": "synthetic",
             "config": {"workload": "two unit-mass Plummer spheres of 2^21 at +-(5,0,0), seeds 3/4; uniform cube "
                                    "2^22 in [-1,1]^3, masses U[0.5,1.5]/N, seed 5; eps 0.005; leaf_cap "
-                                   f"{a.leaf_cap}; monopole at theta 0.3-1.0 and quadrupole at 0.5-1.0",
+                                   f"{a.leaf_cap}; per-body monopole at theta 0.3-1.0, quadrupole and the group "
+                                   "criterion (64-body groups) at 0.5-1.0",
                        "error_sample": f"{a.sample} random targets per system (against the oracle at the same "
                                        "settings, and against direct summation)"},
             "results": rows}
@@ -268,8 +274,8 @@ def serve(a, bh, ctx, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(sharding across GPUs is not built)"}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -1,4 +1,4 @@
-"""Pins of the oracle's group-criterion walk (survey NEXT-3: a cube is accepted for a
+"""Pins of the oracle's group-criterion walk (a cube is accepted for a
 whole group of key-consecutive bodies when it passes against the group's bounding
 box) against facts that do not come from that code: the per-body walk it must
 equal for groups of one, an independent pure-Python group walk on the pointer
