@@ -327,15 +327,17 @@ def main():
         w1.record(stream)
         torch.cuda.synchronize()
         ms_walk = w0.elapsed_time(w1) / a.walk_reps
-        # ---- build + upward alone ----
+        # ---- build + upward alone: rebuilt in the tree's workspace, as inside a step ----
+        tree.rebuild(pos, mass).upward()
+        torch.cuda.synchronize()
         b0 = torch.cuda.Event(enable_timing=True)
         b1 = torch.cuda.Event(enable_timing=True)
         b0.record(stream)
-        t2 = bh.Tree(ctx, pos0, mass, p).upward()
+        for _ in range(a.walk_reps):
+            tree.rebuild(pos0, mass).upward()
         b1.record(stream)
         torch.cuda.synchronize()
-        ms_build = b0.elapsed_time(b1)
-        del t2
+        ms_build = b0.elapsed_time(b1) / a.walk_reps
         st = tree.forces_stats()
         torch.cuda.synchronize()
         tot = st["totals"]

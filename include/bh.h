@@ -138,6 +138,14 @@ size_t bh_workspace_bytes(int64_t n, const bh_params *p);
 bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass,
                    const bh_params *p, void *ws, size_t ws_bytes, bh_tree **out);
 
+/* Octree construction again, in the tree's own workspace, from new positions
+ * and masses of the same n particles (same parameters): what bh_build does
+ * after its one-time set-up (parameter upload and workspace layout), for a
+ * caller that rebuilds every iteration (section 1: the tree is rebuilt each
+ * time step).  pos and mass replace the tree's inputs under bh_build's
+ * conditions; bh_upward must run again before bh_forces.  Asynchronous. */
+bh_status bh_rebuild(bh_ctx *ctx, bh_tree *tree, const double *pos, const double *mass);
+
 /* Upward pass (section 1: centre of mass of each cube): FP64 mass and centre
  * of mass of every node, summed in a fixed order (particles in key order at
  * leaves, children in octant order above), and the walk records. */

@@ -66,6 +66,7 @@ _SIGS = {
     "bh_ctx_sync": ([_VP], C.c_int),
     "bh_workspace_bytes": ([C.c_int64, C.POINTER(Params)], C.c_size_t),
     "bh_build": ([_VP, C.c_int64, _VP, _VP, C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)], C.c_int),
+    "bh_rebuild": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_upward": ([_VP, _VP], C.c_int),
     "bh_forces": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_forces_stats": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)], C.c_int),
@@ -199,6 +200,14 @@ class Tree:
         h = _VP()
         _check(lib().bh_build(ctx.h, n, _ptr(pos), _ptr(mass), C.byref(p), _ptr(self.ws), nb, C.byref(h)))
         self.h = h
+
+    def rebuild(self, pos, mass):
+        """bh_rebuild: the same tree and workspace, new positions and masses of the n particles."""
+        _need(pos, self.n, 3)
+        _need(mass, self.n, 0)
+        self.pos, self.mass = pos, mass
+        _check(lib().bh_rebuild(self.ctx.h, self.h, _ptr(pos), _ptr(mass)))
+        return self
 
     def upward(self):
         _check(lib().bh_upward(self.ctx.h, self.h))

@@ -253,6 +253,23 @@ bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *m
     return BH_OK;
 }
 
+// nsteps KDK steps; between two steps the closing half-kick, the next opening
+// half-kick and its drift run as one fused pass (same roundings, same order).
+bh_status bh_forest_kdk_steps(ForestHost &F, double *pos, double *vel, const double *mass, double *acc,
+                              int32_t nsteps, hipStream_t s) {
+    if (nsteps <= 0) return BH_OK;
+    if (!s) s = F.ctx->stream;
+    HIPCHK(launch_kick(F.dev, vel, acc, 0, s));
+    HIPCHK(launch_drift(F.dev, pos, vel, 0, s));
+    for (int32_t k = 0; k < nsteps; ++k) {
+        if (k > 0) HIPCHK(launch_kick_kick_drift(F.dev, pos, vel, acc, s));
+        bh_status st = bh_forest_eval(F, pos, mass, acc, nullptr, false, s);
+        if (st != BH_OK) return st;
+    }
+    HIPCHK(launch_kick(F.dev, vel, acc, 0, s));
+    return BH_OK;
+}
+
 bh_status bh_forest_check_err(ForestHost &F) {
     uint32_t e = 0;
     HIPCHK(hipMemcpyAsync(&e, F.dev.err, sizeof(uint32_t), hipMemcpyDeviceToHost, F.ctx->stream));
@@ -339,6 +356,15 @@ bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass
         return bh_fail(BH_E_DEVICE, std::string("build launch: ") + hipGetErrorString(e));
     }
     *out = t;
+    return BH_OK;
+}
+
+bh_status bh_rebuild(bh_ctx *ctx, bh_tree *t, const double *pos, const double *mass) {
+    if (!ctx || !t || !pos || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+    t->pos = pos;
+    t->mass = mass;
+    t->upward_done = false;
+    HIPCHK(launch_build(t->F.dev, pos, mass, ctx->stream));
     return BH_OK;
 }
 
@@ -444,11 +470,7 @@ bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
         if (st != BH_OK) return st;
         sm->have_acc = true;
     }
-    for (int32_t k = 0; k < nsteps; ++k) {
-        bh_status st = bh_forest_kdk(sm->F, sm->pos, sm->vel, sm->mass, sm->acc, nullptr);
-        if (st != BH_OK) return st;
-    }
-    return BH_OK;
+    return bh_forest_kdk_steps(sm->F, sm->pos, sm->vel, sm->mass, sm->acc, nsteps, nullptr);
 }
 
 bh_status bh_energy(bh_ctx *ctx, bh_sim *sm, double out_KW[2]) {
@@ -529,11 +551,7 @@ bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const doubl
         if (st != BH_OK) return st;
         fo->have_acc = true;
     }
-    for (int32_t k = 0; k < nsteps; ++k) {
-        st = bh_forest_kdk(fo->F, fo->pos, fo->vel, fo->mass, fo->acc, nullptr);
-        if (st != BH_OK) return st;
-    }
-    return BH_OK;
+    return bh_forest_kdk_steps(fo->F, fo->pos, fo->vel, fo->mass, fo->acc, nsteps, nullptr);
 }
 
 bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *fo, double *pot) {

@@ -250,6 +250,7 @@ hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *ac
 // phase_mask 0: every simulation; else only those whose SegDesc.phase has a bit of the mask.
 hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s);
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);
+hipError_t launch_kick_kick_drift(const ForestDev &f, double *pos, double *vel, const double *acc, hipStream_t s);
 hipError_t launch_energy(const ForestDev &f, const double *vel, const double *mass, const double *pot,
                          double *out2, hipStream_t s);
 hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,

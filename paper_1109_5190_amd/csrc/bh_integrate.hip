@@ -11,38 +11,66 @@ namespace bh {
 
 // ------------------------------------------------------------------ KDK ---
 
-// One block per tile: the tile's simulation decides (phase) whether this half-kick
-// or drift applies to it in this iteration; phase_mask 0 applies it everywhere.
-__global__ void k_kick(ForestDev f, double *vel, const double *acc, uint32_t phase_mask) {
-    const TileDesc td = f.tiles[blockIdx.x];
+// kSub blocks per tile (a tile holds up to 4096 particles, 12288 FP64 words per
+// array), so that a streaming launch keeps enough loads in flight; the tile's
+// simulation decides (phase) whether this half-kick or drift applies to it in
+// this iteration; phase_mask 0 applies it everywhere.
+constexpr uint32_t kSub = 4;
+
+__global__ void __launch_bounds__(256) k_kick(ForestDev f, double *vel, const double *acc, uint32_t phase_mask) {
+    const TileDesc td = f.tiles[blockIdx.x / kSub];
     const SegDesc &sd = f.seg[td.seg];
     if (phase_mask && !(sd.phase & phase_mask)) return;
     double *vb = seg_base(vel, sd.vel, sd, 3);
     const double *ab = seg_base(acc, (const double *)sd.acc, sd, 3);
     const double h = __dmul_rn(0.5, sd.dt);
     const size_t j0 = 3 * (size_t)(td.start - sd.start);
-    for (uint32_t j = threadIdx.x; j < 3 * td.count; j += blockDim.x)
+    for (uint32_t j = (blockIdx.x % kSub) * 256 + threadIdx.x; j < 3 * td.count; j += 256 * kSub)
         vb[j0 + j] = __dadd_rn(vb[j0 + j], __dmul_rn(h, ab[j0 + j]));
 }
 
-__global__ void k_drift(ForestDev f, double *pos, const double *vel, uint32_t phase_mask) {
-    const TileDesc td = f.tiles[blockIdx.x];
+__global__ void __launch_bounds__(256) k_drift(ForestDev f, double *pos, const double *vel, uint32_t phase_mask) {
+    const TileDesc td = f.tiles[blockIdx.x / kSub];
     const SegDesc &sd = f.seg[td.seg];
     if (phase_mask && !(sd.phase & phase_mask)) return;
     double *pb = seg_base(pos, (double *)sd.pos, sd, 3);
     const double *vb = seg_base(vel, (const double *)sd.vel, sd, 3);
     const size_t j0 = 3 * (size_t)(td.start - sd.start);
-    for (uint32_t j = threadIdx.x; j < 3 * td.count; j += blockDim.x)
+    for (uint32_t j = (blockIdx.x % kSub) * 256 + threadIdx.x; j < 3 * td.count; j += 256 * kSub)
         pb[j0 + j] = __dadd_rn(pb[j0 + j], __dmul_rn(sd.dt, vb[j0 + j]));
 }
 
+// The closing half-kick of one step, the opening half-kick of the next and its
+// drift in one pass over the state: the same three roundings, in the same
+// order, as k_kick, k_kick, k_drift.
+__global__ void __launch_bounds__(256) k_kick_kick_drift(ForestDev f, double *pos, double *vel, const double *acc) {
+    const TileDesc td = f.tiles[blockIdx.x / kSub];
+    const SegDesc &sd = f.seg[td.seg];
+    double *pb = seg_base(pos, (double *)sd.pos, sd, 3);
+    double *vb = seg_base(vel, sd.vel, sd, 3);
+    const double *ab = seg_base(acc, (const double *)sd.acc, sd, 3);
+    const double h = __dmul_rn(0.5, sd.dt);
+    const size_t j0 = 3 * (size_t)(td.start - sd.start);
+    for (uint32_t j = (blockIdx.x % kSub) * 256 + threadIdx.x; j < 3 * td.count; j += 256 * kSub) {
+        const double ha = __dmul_rn(h, ab[j0 + j]);
+        const double v = __dadd_rn(__dadd_rn(vb[j0 + j], ha), ha);
+        vb[j0 + j] = v;
+        pb[j0 + j] = __dadd_rn(pb[j0 + j], __dmul_rn(sd.dt, v));
+    }
+}
+
 hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s) {
-    if (f.ntiles) hipLaunchKernelGGL(k_kick, dim3(f.ntiles), dim3(256), 0, s, f, vel, acc, phase_mask);
+    if (f.ntiles) hipLaunchKernelGGL(k_kick, dim3(f.ntiles * kSub), dim3(256), 0, s, f, vel, acc, phase_mask);
     return hipGetLastError();
 }
 
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s) {
-    if (f.ntiles) hipLaunchKernelGGL(k_drift, dim3(f.ntiles), dim3(256), 0, s, f, pos, vel, phase_mask);
+    if (f.ntiles) hipLaunchKernelGGL(k_drift, dim3(f.ntiles * kSub), dim3(256), 0, s, f, pos, vel, phase_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_kick_drift(const ForestDev &f, double *pos, double *vel, const double *acc, hipStream_t s) {
+    if (f.ntiles) hipLaunchKernelGGL(k_kick_kick_drift, dim3(f.ntiles * kSub), dim3(256), 0, s, f, pos, vel, acc);
     return hipGetLastError();
 }
 

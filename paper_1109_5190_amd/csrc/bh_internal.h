@@ -67,4 +67,6 @@ bh_status bh_forest_upload_seg(ForestHost &F);
 bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, double *acc, double *pot,
                          bool want_pot, hipStream_t s);
 bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *mass, double *acc, hipStream_t s);
+bh_status bh_forest_kdk_steps(ForestHost &F, double *pos, double *vel, const double *mass, double *acc,
+                              int32_t nsteps, hipStream_t s);
 bh_status bh_forest_check_err(ForestHost &F);

@@ -137,3 +137,24 @@ def test_forces_plain_equals_stats_variant(ctx):
         r = t.forces_stats()
         ctx.sync()
         assert torch.equal(a, r["acc"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rebuild_equals_fresh_tree(ctx, prec):
+    """bh_rebuild in the workspace of a tree built on other positions (a different root cube and
+    node count) gives the fresh build's tree and forces bit for bit, and the oracle's tree."""
+    a, b = icgen.plummer(6000, 21), icgen.uniform_cube(6000, 22)
+    p = bh.params(0.6, 0.01, precision=prec)
+    t = bh.Tree(ctx, dev(a.pos), dev(a.mass), p).upward()
+    t.forces()
+    pos_b, mass_b = dev(b.pos), dev(b.mass)
+    t.rebuild(pos_b, mass_b).upward()
+    fresh = bh.Tree(ctx, pos_b, mass_b, p).upward()
+    ex, ef = t.export(), fresh.export()
+    ctx.sync()
+    T = oracle.Tree(b.pos, b.mass, 1)
+    assert ex["n_nodes"] == ef["n_nodes"] == T.nn
+    for k in ("keys", "perm", "level", "first", "count", "parent", "M", "com"):
+        assert torch.equal(ex[k], ef[k]), k
+    assert np.array_equal(ex["com"].cpu().numpy(), T.com)
+    assert torch.equal(t.forces(), fresh.forces())
