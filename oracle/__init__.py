@@ -26,7 +26,7 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double), ("leaf_cap", C.c_int32),
-                ("quad", C.c_int32)]
+                ("quad", C.c_int32), ("open", C.c_int32)]
 
 
 def build(force: bool = True) -> Path:
@@ -74,6 +74,8 @@ def lib():
         L.or_kdk.argtypes = [C.c_int64, _f64p, _f64p, _f64p, C.POINTER(Params), C.c_double, C.c_int32,
                              _f64p, C.c_int32, C.c_void_p, C.c_int]
         L.or_energy.argtypes = [C.c_int64, _f64p, _f64p, C.c_void_p, _f64p]
+        L.or_open_r2.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int32]
+        L.or_open_r2.restype = C.c_double
         L.or_mix64.argtypes = [C.c_uint64]
         L.or_mix64.restype = C.c_uint64
         _lib = L
@@ -119,8 +121,12 @@ def order(keys_):
     return perm
 
 
-def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, quad=False):
-    return Params(float(theta), float(eps), float(G), int(leaf_cap), int(bool(quad)))
+OPEN = {"side": 0, "bmax": 1, "offset": 2}
+
+
+def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, quad=False, open="side"):
+    """open: the opening radius r of r^2 < theta^2 D^2 ("side", "bmax" or "offset")."""
+    return Params(float(theta), float(eps), float(G), int(leaf_cap), int(bool(quad)), OPEN[open])
 
 
 class Tree:
@@ -158,8 +164,13 @@ class Tree:
         lib().or_tree_moments(self._h, out)
         return out
 
-    def walk(self, theta=0.5, eps=0.01, G=1.0, targets=None, nthreads=0, quad=False):
-        p = params(theta, eps, G, 1, quad)
+    def open_r2(self, theta, open):
+        """r^2 of every node under the opening variant `open` (see or_open_r2)."""
+        p = params(theta, 0.0, 1.0, 1, False, open)
+        return np.array([lib().or_open_r2(self._h, C.byref(p), i) for i in range(self.nn)])
+
+    def walk(self, theta=0.5, eps=0.01, G=1.0, targets=None, nthreads=0, quad=False, open="side"):
+        p = params(theta, eps, G, 1, quad, open)
         t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
         nt = self.n if t is None else t.shape[0]
         acc = np.zeros((nt, 3))
@@ -196,9 +207,10 @@ class Tree:
             self._h = None
 
 
-def forces(pos, mass, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, targets=None, nthreads=0, quad=False):
+def forces(pos, mass, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, targets=None, nthreads=0, quad=False,
+           open="side"):
     t = Tree(pos, mass, leaf_cap)
-    return t.walk(theta, eps, G, targets, nthreads, quad)
+    return t.walk(theta, eps, G, targets, nthreads, quad, open)
 
 
 def direct(pos, mass, eps=0.01, G=1.0, targets=None, nthreads=0):
@@ -213,7 +225,8 @@ def direct(pos, mass, eps=0.01, G=1.0, targets=None, nthreads=0):
     return dict(acc=acc, pot=pot)
 
 
-def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=None, nthreads=0, quad=False):
+def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=None, nthreads=0, quad=False,
+        open="side"):
     """Returns (pos, vel, acc, pot) after nsteps leapfrog steps (copies; inputs untouched)."""
     pos = _f64(pos, (-1, 3)).copy()
     vel = _f64(vel, (-1, 3)).copy()
@@ -221,7 +234,7 @@ def kdk(pos, vel, mass, dt, nsteps, theta=0.5, eps=0.01, G=1.0, leaf_cap=1, acc=
     have = acc is not None
     a = _f64(acc, (-1, 3)).copy() if have else np.zeros_like(pos)
     pot = np.zeros(pos.shape[0])
-    p = params(theta, eps, G, leaf_cap, quad)
+    p = params(theta, eps, G, leaf_cap, quad, open)
     rc = lib().or_kdk(pos.shape[0], pos, vel, mass, C.byref(p), float(dt), int(nsteps), a, int(have),
                       _ptr(pot), int(nthreads))
     if rc:

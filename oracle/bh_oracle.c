@@ -326,6 +326,42 @@ static void interact_quad(const double x[3], const double c[3], const double S[6
 
 #define WALK_STACK 256
 
+/* quantised coordinate of axis a (0 = x, the most significant bit of each triple) */
+static uint32_t key_coord(uint64_t key, int a)
+{
+    uint32_t q = 0;
+    for (int b = 0; b < OR_MAX_LEVEL; b++) q |= (uint32_t)((key >> (3 * b + 2 - a)) & 1u) << b;
+    return q;
+}
+
+double or_open_r2(const or_tree *t, const or_params *p, int32_t id)
+{
+    const double L = ldexp(1.0, t->k), h = ldexp(1.0, t->k - OR_MAX_LEVEL);
+    const int l = t->level[id];
+    const double s = ldexp(L, -l);
+    if (p->open == OR_OPEN_SIDE) return s * s;
+    const uint64_t key = t->keys[t->first[id]];
+    const uint32_t w = 1u << (OR_MAX_LEVEL - l);
+    const double *c = &t->com[3 * id];
+    double e[3];
+    for (int a = 0; a < 3; a++) {
+        const uint32_t Q = key_coord(key, a) & ~(w - 1u);
+        if (p->open == OR_OPEN_BMAX) {
+            const double lo = t->lo[a] + (double)Q * h;
+            const double hi = t->lo[a] + (double)(Q + w) * h;
+            const double u = c[a] - lo, v = hi - c[a];
+            e[a] = u > v ? u : v;
+        } else {
+            const double ctr = t->lo[a] + (double)(2u * Q + w) * (0.5 * h);
+            e[a] = c[a] - ctr;
+        }
+    }
+    const double e2 = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+    if (p->open == OR_OPEN_BMAX) return e2;
+    const double r = s + p->theta * sqrt(e2);
+    return r * r;
+}
+
 /* ---- the walk for one body (original index i, position x) ---- */
 static void walk_one(const or_tree *t, int64_t i, const double x[3], const or_params *p,
                      double a[3], double *phi, int64_t *nm, int64_t *np, uint64_t *h)
@@ -345,7 +381,8 @@ static void walk_one(const or_tree *t, int64_t i, const double x[3], const or_pa
         double dx = c[0] - x[0], dy = c[1] - x[1], dz = c[2] - x[2];
         double D2 = (dx * dx + dy * dy) + dz * dz;
         double s = ldexp(L, -t->level[id]);
-        if (s * s < theta2 * D2) {
+        double r2 = p->open == OR_OPEN_SIDE ? s * s : or_open_r2(t, p, id);
+        if (r2 < theta2 * D2) {
             interact(x, c, t->M[id], eps2, p->G, a, phi);
             if (p->quad) interact_quad(x, c, &t->S2[6 * id], eps2, p->G, a, phi);
             (*nm)++;
@@ -370,6 +407,7 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
                  int64_t *n_p2p, uint64_t *hash, int nthreads)
 {
     if (!t || !p || !(p->theta >= 0.0) || !(p->eps >= 0.0)) return 1;
+    if (p->open < OR_OPEN_SIDE || p->open > OR_OPEN_OFFSET) return 1;
     if (!targets) ntarget = t->n;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -409,6 +447,7 @@ int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int6
                        int64_t *n_p2p, uint64_t *hash, int nthreads)
 {
     if (!t || !p || group < 1 || !(p->theta >= 0.0) || !(p->eps >= 0.0)) return 1;
+    if (p->open != OR_OPEN_SIDE) return 1;   /* the group test is defined with the side only */
     const int64_t n = t->n;
     double *A = (double *)malloc(sizeof(double) * 3 * n), *P = (double *)malloc(sizeof(double) * n);
     int64_t *NM = (int64_t *)malloc(sizeof(int64_t) * n), *NP = (int64_t *)malloc(sizeof(int64_t) * n);

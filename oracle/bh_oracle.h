@@ -37,7 +37,20 @@ typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;
     int32_t quad;           /* 1: accepted cubes add their quadrupole term (see or_tree_moments) */
+    int32_t open;           /* opening radius r of the test r^2 < theta^2 D^2: OR_OPEN_* */
 } or_params;
+
+/* Alternative ways of computing the opening criterion (section 6 lists them as
+ * future work).  The test stays r*r < (theta*theta) * D2 with D2 as in the walk:
+ *   OR_OPEN_SIDE   r = the cube side s (the paper's reading, the default);
+ *   OR_OPEN_BMAX   r = the largest distance from the centre of mass to a corner
+ *                  of the cube (Salmon and Warren's b_max);
+ *   OR_OPEN_OFFSET accept iff D > s/theta + delta, delta the distance from the
+ *                  centre of mass to the cube's geometric centre (Barnes 1994),
+ *                  i.e. r = s + theta delta. */
+#define OR_OPEN_SIDE 0
+#define OR_OPEN_BMAX 1
+#define OR_OPEN_OFFSET 2
 
 typedef struct {
     int64_t n, nn;          /* particles, tree nodes */
@@ -73,6 +86,16 @@ void or_tree_export(const or_tree *t, double lo[3], int32_t *k, uint64_t *keys, 
  * order (nn x 6: xx yy zz xy xz yz).  They carry the quadrupole of the cube's mass
  * distribution: the paper names multipole moments as future work (section 6). */
 void or_tree_moments(const or_tree *t, double *S6);
+
+/* r^2 of node id under p->open, in FP64.  Cube geometry of a level-l node: with
+ * (qx, qy, qz) the quantised coordinates of its first key, low 21 - l bits
+ * cleared (Q), h = L 2^-21 and w = 2^(21-l): corner lo = fl(root_lo + Q h),
+ * far corner hi = fl(root_lo + (Q + w) h), centre fl(root_lo + (2Q + w) h/2),
+ * each a single rounding of an exact product.  b_max: e = max(c - lo, hi - c)
+ * per axis, r^2 = (ex*ex + ey*ey) + ez*ez.  Offset: d = c - centre per axis,
+ * delta = sqrt((dx*dx + dy*dy) + dz*dz), r = s + theta*delta, r^2 = r*r.
+ * Side: r^2 = s*s. */
+double or_open_r2(const or_tree *t, const or_params *p, int32_t id);
 
 /* walk for the given targets (original indices; NULL = all n in index order).
  * Outputs are indexed by target slot.  Any output may be NULL. */

@@ -87,8 +87,9 @@ def build(pos, mass, leaf_cap=1):
     return root, nodes, lo, L
 
 
-def walk(root, nodes, pos, mass, L, i, theta, eps, G=1.0):
-    """Recursive BH force on body i.  Returns (acc, accepted node ids, pair partner ids)."""
+def walk(root, nodes, pos, mass, L, i, theta, eps, G=1.0, radius2=None):
+    """Recursive BH force on body i.  Returns (acc, accepted node ids, pair partner ids).
+    radius2(node, side) gives r^2 of the test r^2 < theta^2 D^2 (default: side^2)."""
     x = [float(v) for v in pos[i]]
     acc = [0.0, 0.0, 0.0]
     mono, pairs = [], []
@@ -105,7 +106,8 @@ def walk(root, nodes, pos, mass, L, i, theta, eps, G=1.0):
     def visit(nd):
         D2 = sum((nd.com[c] - x[c]) ** 2 for c in range(3))
         s = L / 2 ** nd.level
-        if s * s < theta * theta * D2:
+        r2 = s * s if radius2 is None else radius2(nd, s)
+        if r2 < theta * theta * D2:
             add(nd.com, nd.M)
             mono.append(nd.pre)
         elif not nd.children:
