@@ -82,12 +82,26 @@ typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
  *              with every particle but the body itself.  More conservative (and more
  *              accurate) than the per-body test; all lanes of a wavefront take part in
  *              every cube.  Not combined with BH_QUADRUPOLE.
+ *            BH_OPEN_BMAX: alternative opening radius (section 6 names other ways of
+ *              computing the criterion as future work): accept iff r^2 < theta^2 D^2
+ *              with r = b_max, the largest distance from the cube's centre of mass to
+ *              a corner of the cube, in FP64 as ((ex*ex + ey*ey) + ez*ez) with
+ *              e = max(c - lo, hi - c) per axis.  For theta < 1 no cube holding the
+ *              body is ever accepted.
+ *            BH_OPEN_OFFSET: accept iff D > side/theta + delta, delta the distance
+ *              from the centre of mass to the cube's centre, i.e. r = side + theta
+ *              delta in the same test.  Cube corners and centres are
+ *              root_lo + (integer) * 2^(k-21) from the node's key, one rounding each.
+ *              BH_OPEN_BMAX and BH_OPEN_OFFSET exclude each other and
+ *              BH_GROUP_CRITERION.
  *            BH_REQ_RELEASE (server requests only): free the request's state when it
  *              completes (its energies stay available; bh_server_fetch is then refused).
  *            Other bits are rejected (BH_E_INVAL). */
 #define BH_REQ_RELEASE 1u
 #define BH_QUADRUPOLE 2u
 #define BH_GROUP_CRITERION 4u
+#define BH_OPEN_BMAX 8u
+#define BH_OPEN_OFFSET 16u
 typedef struct {
     double theta, eps, G;
     int32_t leaf_cap;

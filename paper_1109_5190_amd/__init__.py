@@ -33,11 +33,17 @@ class Params(C.Structure):
 
 QUADRUPOLE = 2
 GROUP_CRITERION = 4
+OPEN_BMAX = 8
+OPEN_OFFSET = 16
+OPEN = {"side": 0, "bmax": OPEN_BMAX, "offset": OPEN_OFFSET}
 
 
-def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False, group=False) -> Params:
+def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False, group=False,
+           open="side") -> Params:
+    """open: opening radius of the test r^2 < theta^2 D^2: "side" (the cube side), "bmax"
+    (BH_OPEN_BMAX) or "offset" (BH_OPEN_OFFSET)."""
     prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
-    flags = (QUADRUPOLE if quad else 0) | (GROUP_CRITERION if group else 0)
+    flags = (QUADRUPOLE if quad else 0) | (GROUP_CRITERION if group else 0) | OPEN[open]
     return Params(float(theta), float(eps), float(G), int(leaf_cap), prec, flags, 0)
 
 

@@ -35,10 +35,14 @@ bh_status bh_check_params(const bh_params *p) {
     if (!std::isfinite(p->G)) return bh_fail(BH_E_INVAL, "G must be finite");
     if (p->leaf_cap < 1 || p->leaf_cap > 64) return bh_fail(BH_E_INVAL, "leaf_cap must be in [1, 64]");
     if (p->precision != BH_FP64 && p->precision != BH_FP32) return bh_fail(BH_E_INVAL, "precision must be BH_FP64 or BH_FP32");
-    if (p->flags & ~(uint32_t)(BH_QUADRUPOLE | BH_GROUP_CRITERION | BH_REQ_RELEASE))
+    if (p->flags & ~(uint32_t)(BH_QUADRUPOLE | BH_GROUP_CRITERION | BH_OPEN_BMAX | BH_OPEN_OFFSET | BH_REQ_RELEASE))
         return bh_fail(BH_E_INVAL, "unknown bits in flags");
     if ((p->flags & BH_QUADRUPOLE) && (p->flags & BH_GROUP_CRITERION))
         return bh_fail(BH_E_INVAL, "BH_QUADRUPOLE and BH_GROUP_CRITERION are not combined");
+    if ((p->flags & BH_OPEN_BMAX) && (p->flags & BH_OPEN_OFFSET))
+        return bh_fail(BH_E_INVAL, "BH_OPEN_BMAX and BH_OPEN_OFFSET exclude each other");
+    if ((p->flags & (BH_OPEN_BMAX | BH_OPEN_OFFSET)) && (p->flags & BH_GROUP_CRITERION))
+        return bh_fail(BH_E_INVAL, "the group criterion is defined with the cube side only");
     return BH_OK;
 }
 
@@ -84,6 +88,7 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.dt = 0.0;
         d.quad = (p[s].flags & BH_QUADRUPOLE) ? 1u : 0u;
         d.group = (p[s].flags & BH_GROUP_CRITERION) ? 1u : 0u;
+        d.open = (p[s].flags & BH_OPEN_BMAX) ? kOpenBmax : (p[s].flags & BH_OPEN_OFFSET) ? kOpenOffset : kOpenSide;
         (p[s].precision == BH_FP32 ? has32 : has64) |= d.group ? kVarGroup : var_bit(d.quad != 0, unsoftened(d.eps));
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;

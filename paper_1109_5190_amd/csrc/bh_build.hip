@@ -806,6 +806,39 @@ __global__ void __launch_bounds__(256) k_up_level(ForestDev f, int level, uint32
     }
 }
 
+// r^2 of the opening test r^2 < theta^2 D^2 of a level-`level` cube whose first
+// key is `key`, centre of mass c and side s (paper section 3 uses the side;
+// section 6 lists other ways of computing the criterion as future work).
+// Cube geometry from the key: Q = the cube's integer corner (low 21 - level bits
+// of each quantised coordinate cleared), h = L 2^-21, w = 2^(21 - level):
+// corner lo + Q h, far corner lo + (Q + w) h, centre lo + (2Q + w) h/2, each one
+// rounding of an exact product.  b_max: e = max(c - corner, far - c) per axis,
+// r^2 = (ex^2 + ey^2) + ez^2.  Offset (D > s/theta + delta): delta = |c - centre|,
+// r = s + theta delta.
+__device__ double open_radius2(uint64_t key, int level, const double c[3], double s, const SegState &st,
+                               const SegDesc &sd) {
+    if (sd.open == kOpenSide) return __dmul_rn(s, s);
+    const double h = ldexp(st.L, -kMaxLevel);
+    const uint32_t w = 1u << (kMaxLevel - level);
+    double e[3];
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t Q = compact3(key >> (2 - a)) & ~(w - 1u);
+        if (sd.open == kOpenBmax) {
+            const double lo = __dadd_rn(st.lo[a], __dmul_rn((double)Q, h));
+            const double hi = __dadd_rn(st.lo[a], __dmul_rn((double)(Q + w), h));
+            const double u = __dsub_rn(c[a], lo), v = __dsub_rn(hi, c[a]);
+            e[a] = u > v ? u : v;
+        } else {
+            const double ctr = __dadd_rn(st.lo[a], __dmul_rn((double)(2u * Q + w), __dmul_rn(0.5, h)));
+            e[a] = __dsub_rn(c[a], ctr);
+        }
+    }
+    const double e2 = __dadd_rn(__dadd_rn(__dmul_rn(e[0], e[0]), __dmul_rn(e[1], e[1])), __dmul_rn(e[2], e[2]));
+    if (sd.open == kOpenBmax) return e2;
+    const double r = __dadd_rn(s, __dmul_rn(sd.theta, __dsqrt_rn(e2)));
+    return __dmul_rn(r, r);
+}
+
 // com = S / M, then the walk record of the node at its slot.
 __global__ void k_records(ForestDev f) {
     uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -836,13 +869,14 @@ __global__ void k_records(ForestDev f) {
         return;
     }
     const double s = ldexp(st.L, -level);
+    const double r2 = open_radius2(f.keys[f.nfirst[g]], level, c, s, st, sd);
     if (sd.precision == 1) {
         WRec32 w;
         w.cx = c[0];
         w.cy = c[1];
         w.cz = c[2];
         w.m = (float)M;
-        // FP32 opening test: accept iff |d|^2 + eps^2 > side^2 / theta^2 + eps^2 (the walk adds
+        // FP32 opening test: accept iff |d|^2 + eps^2 > r^2 / theta^2 + eps^2 (the walk adds
         // its rounding band); S is kept only when it and eps^2 are well inside the FP32 range,
         // otherwise every test of this node is decided in FP64.
         const double u = 5.9604644775390625e-8;   // 2^-24
@@ -854,11 +888,11 @@ __global__ void k_records(ForestDev f) {
             w.band0 = 0.0f;
             w.band1 = 0.0f;
         } else {
-            const double S = s * s / (sd.theta * sd.theta) + eps2;
-            if (eps_ok && s * s > 1e-30 && S > 1e-30 && S < 1e30) {
+            const double S = r2 / (sd.theta * sd.theta) + eps2;
+            if (eps_ok && r2 > 1e-30 && S > 1e-30 && S < 1e30) {
                 w.Sp = (float)S;
                 w.band0 = (float)(16.0 * u * S * (1.0 + 1e-6));
-                w.band1 = (float)(8.0 * u * s / sd.theta * (1.0 + 1e-6));
+                w.band1 = (float)(8.0 * u * sqrt(r2) / sd.theta * (1.0 + 1e-6));
             } else {
                 w.Sp = 0.0f;
                 w.band0 = INFINITY;
@@ -869,7 +903,7 @@ __global__ void k_records(ForestDev f) {
         w.cnt = cnt;
         w.gid = g;
         w.level = (uint32_t)level;
-        w.pad[0] = w.pad[1] = 0;
+        w.r2 = r2;
         f.w32[sl] = w;
         if (sd.quad) {
             const double *q = f.uQ + 6 * (size_t)sl;
@@ -882,7 +916,7 @@ __global__ void k_records(ForestDev f) {
         w.y = c[1];
         w.z = c[2];
         w.m = M;
-        w.S = __dmul_rn(s, s);
+        w.S = r2;
         w.link = link;
         w.cnt = cnt;
         w.gid = g;

@@ -35,8 +35,10 @@ struct SegDesc {
     uint32_t phase;             // kPhase* bits: which parts of a step apply this iteration
     uint32_t quad;              // 1: accepted cubes add their quadrupole term
     uint32_t group;             // 1: group criterion (a cube is accepted for the whole walk group)
-    uint32_t pad;
+    uint32_t open;              // kOpen*: opening radius r of the test r^2 < theta^2 D^2
 };
+
+constexpr uint32_t kOpenSide = 0u, kOpenBmax = 1u, kOpenOffset = 2u;
 
 constexpr uint32_t kPhaseDrift = 1u, kPhaseKick2 = 2u, kPhaseKick1 = 4u;
 
@@ -61,23 +63,24 @@ struct GroupDesc { uint32_t start, count, seg, pad; };
 struct WRec32 {
     double cx, cy, cz;         // centre of mass (FP64)
     float m;                   // mass (FP32)
-    float Sp;                  // S = side^2 / theta^2 + eps^2 (FP32; +inf when theta = 0)
+    float Sp;                  // S = r^2 / theta^2 + eps^2 (FP32; +inf when theta = 0)
     float band0;               // 16 u S (inf: S outside FP32 range, always decide in FP64)
-    float band1;               // 8 u side / theta
+    float band1;               // 8 u r / theta
     uint32_t link;             // internal: first child slot; leaf: first particle rank
     uint32_t cnt;              // internal: children; leaf: particles | kLeafBit
     uint32_t gid;              // global node id (depth-first preorder)
     uint32_t level;
-    uint32_t pad[2];
+    double r2;                 // r^2 of the exact FP64 test r^2 < theta^2 D^2 (side^2 by default)
 };
 
 // Walk record of a node, FP64 mode.
 struct WRec64 {
     double x, y, z, m;
-    double S;
+    double S;                  // r^2 of the test r^2 < theta^2 D^2 (side^2 by default)
     uint32_t link, cnt, gid, level;
     double pad;
 };
+static_assert(sizeof(WRec32) == 64 && sizeof(WRec64) == 64, "walk records are one 64-byte line");
 
 // Device-side views of one forest's buffers (all sub-allocated from the caller's workspace).
 struct ForestDev {
@@ -148,6 +151,17 @@ __device__ __forceinline__ unsigned long long ord_enc(double v) {
 __device__ __forceinline__ double ord_dec(unsigned long long e) {
     unsigned long long b = (e & 0x8000000000000000ull) ? (e & 0x7fffffffffffffffull) : ~e;
     return __longlong_as_double((long long)b);
+}
+
+// Inverse of spread3: bits 3b of v gathered to bit b.
+__device__ __forceinline__ uint32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x001f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x001f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x00000000001fffffull;
+    return (uint32_t)v;
 }
 
 // Morton spread: bit b of v moves to bit 3b (v < 2^21).

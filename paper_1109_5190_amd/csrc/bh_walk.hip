@@ -291,8 +291,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                                      ez = __dsub_rn(cm[2], xp[2]);
                         const double ED2 =
                             __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
-                        const double s = ldexp(st.L, -(int)qc.y);
-                        ex = __dmul_rn(s, s) < __dmul_rn(__dmul_rn(theta, theta), ED2);
+                        ex = f.w32[link + c].r2 < __dmul_rn(__dmul_rn(theta, theta), ED2);
                         if (STATS) ++nfb;
                     }
                     accm |= ballot(ex) & ambm;

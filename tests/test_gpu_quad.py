@@ -99,6 +99,6 @@ def test_forest_mixing_orders_equals_alone(ctx):
 def test_flags_validated(ctx):
     s = icgen.plummer(100, 1)
     p = bh.params(0.5, 0.01)
-    p.flags = 8
+    p.flags = 1 << 10
     with pytest.raises(bh.BHError):
         bh.Tree(ctx, dev(s.pos), dev(s.mass), p)
