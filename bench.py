@@ -111,17 +111,18 @@ def sweep(a, bh, torch):
         tg = np.sort(rng.choice(s.n, min(a.sample, s.n), replace=False)).astype(np.int64)
         tgd = torch.tensor(tg, device=dev)
         exact = oracle.direct(s.pos, s.mass, eps=0.005, targets=tg, nthreads=cores)["acc"]
-        runs = ([(th, "monopole") for th in (0.3, 0.5, 0.7, 1.0)] + [(th, "quadrupole") for th in (0.5, 0.7, 1.0)]
-                + [(th, "group") for th in (0.5, 0.7, 1.0)])
+        runs = ([(th, "monopole") for th in (0.3, 0.5, 0.7, 1.0)]
+                + [(th, v) for v in ("quadrupole", "bmax", "offset", "group") for th in (0.5, 0.7, 1.0)])
         for theta, variant in runs:
             quad, group = variant == "quadrupole", variant == "group"
+            open_ = variant if variant in ("bmax", "offset") else "side"
             if group:
                 ref = T.walk_group(theta, 0.005, 1.0, 64, tg, nthreads=cores)
             else:
-                ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores, quad=quad)
+                ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores, quad=quad, open=open_)
             inter = None
             for prec in ("fp32", "fp64"):
-                p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec, quad=quad, group=group)
+                p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec, quad=quad, group=group, open=open_)
                 t = bh.Tree(ctx, pos, mass, p).upward()
                 acc = t.forces()
                 if inter is None:
@@ -164,8 +165,9 @@ def sweep(a, bh, torch):
             "unit": "Mparticles/s", "n_gpus": 1, "data": "synthetic",
             "config": {"workload": "two unit-mass Plummer spheres of 2^21 at +-(5,0,0), seeds 3/4; uniform cube "
                                    "2^22 in [-1,1]^3, masses U[0.5,1.5]/N, seed 5; eps 0.005; leaf_cap "
-                                   f"{a.leaf_cap}; per-body monopole at theta 0.3-1.0, quadrupole and the group "
-                                   "criterion (64-body groups) at 0.5-1.0",
+                                   f"{a.leaf_cap}; per-body monopole at theta 0.3-1.0; at 0.5-1.0 the quadrupole, "
+                                   "the b_max and centre-offset opening radii, and the group criterion "
+                                   "(64-body groups)",
                        "error_sample": f"{a.sample} random targets per system (against the oracle at the same "
                                        "settings, and against direct summation)"},
             "results": rows}
