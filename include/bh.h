@@ -179,6 +179,50 @@ bh_status bh_forces(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot);
 bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, int64_t *n_mono,
                           int64_t *n_p2p, uint64_t *hash, bh_stats *totals);
 
+/* ------------------------------------------------------ interaction lists --- */
+
+/* Two-phase force stage, the paper's own structure (section 3: each body's
+ * interaction list of cubes and bodies is formed, flattened, then evaluated).
+ * Phase one, bh_lists_build, walks the tree with bh_forces's decisions and
+ * writes the lists into a caller buffer; phase two, bh_lists_forces, evaluates
+ * them and gives bh_forces's acc and pot bit for bit.  FP32 trees with the
+ * monopole expansion and the per-body test (any opening radius) only;
+ * otherwise BH_E_INVAL.
+ *
+ * Lists are kept per walk group: group g holds the bodies of sorted ranks
+ * [64 g, min(64 g + 64, n)); bit k of a mask is the group's k-th body.
+ * Entry (a, b, mask), in walk order:
+ *   a == 0xffffffff        start of a stack entry with b children (it times
+ *                          the compensated-sum folds);
+ *   b & 0x80000000         an opened leaf: particles of sorted ranks
+ *                          [a, a + (b & 0x7fffffff)), paired with the bodies
+ *                          in mask (not with themselves);
+ *   otherwise              an accepted cube: walk slot a, node b (global
+ *                          preorder id), for the bodies in mask.
+ * Buffer layout (device memory, 256-byte aligned, `bytes` long; G groups and
+ * C chunks of 64 entries, C the largest count that fits):
+ *   byte 0:                 uint64, chunks the last build took;
+ *   byte 256:               uint32 head[G], first chunk of each group;
+ *   next 256-byte boundary: uint32 count[G], entries of each group;
+ *   next 256-byte boundary: uint32 next[C], the group's next chunk
+ *                           (0xffffffff: last);
+ *   next 256-byte boundary: bh_list_entry entries[64 C].
+ * The lists stay owned by the caller and valid until the tree is rebuilt or
+ * its upward pass runs again. */
+typedef struct {
+    uint32_t a, b;
+    uint64_t mask;
+} bh_list_entry;
+
+/* Phase one.  SYNC.  *bytes_needed (nullable) receives the buffer size these
+ * lists need; when it exceeds `bytes` the call returns BH_E_NOMEM and the
+ * buffer holds no usable lists (call again with a larger buffer). */
+bh_status bh_lists_build(bh_ctx *ctx, bh_tree *tree, void *buf, size_t bytes, size_t *bytes_needed);
+
+/* Phase two over the lists the last successful bh_lists_build of this tree
+ * wrote into buf: acc (n x 3) and pot (nullable) as bh_forces.  Asynchronous. */
+bh_status bh_lists_forces(bh_ctx *ctx, bh_tree *tree, const void *buf, double *acc, double *pot);
+
 /* SYNC.  Number of tree nodes and the root cube (lo[3] host, k: side 2^k). */
 bh_status bh_tree_info(bh_ctx *ctx, bh_tree *tree, int64_t *n_nodes, double lo[3], int32_t *k);
 

@@ -74,6 +74,8 @@ _SIGS = {
     "bh_build": ([_VP, C.c_int64, _VP, _VP, C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)], C.c_int),
     "bh_rebuild": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_upward": ([_VP, _VP], C.c_int),
+    "bh_lists_build": ([_VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+    "bh_lists_forces": ([_VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_forces": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_forces_stats": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)], C.c_int),
     "bh_tree_info": ([_VP, _VP, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
@@ -218,6 +220,33 @@ class Tree:
     def upward(self):
         _check(lib().bh_upward(self.ctx.h, self.h))
         return self
+
+    def lists_build(self, nbytes=None):
+        """bh_lists_build into a torch-owned buffer (grown to the size the call reports if it is
+        too small).  Returns the buffer (uint8, 256-byte aligned view), kept for lists_forces."""
+        torch = _torch()
+        nbytes = int(nbytes or 4096 * (self.n // 64 + 1) * 16 + (1 << 20))
+        for _ in range(2):
+            raw, buf = workspace(nbytes, self.pos.device)
+            need = C.c_size_t(0)
+            st = lib().bh_lists_build(self.ctx.h, self.h, _ptr(buf), buf.numel(), C.byref(need))
+            if st == OK:
+                self._lists = (raw, buf)
+                return buf
+            if st != E_NOMEM:
+                _check(st)
+            nbytes = int(need.value) + 256
+        _check(st)
+
+    def lists_forces(self, acc=None, pot=False):
+        """bh_lists_forces over the buffer of the last lists_build."""
+        torch = _torch()
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float64, device=self.pos.device)
+        ph = torch.empty(self.n, dtype=torch.float64, device=self.pos.device) if pot else None
+        buf = self._lists[1] if getattr(self, "_lists", None) else None
+        _check(lib().bh_lists_forces(self.ctx.h, self.h, _ptr(buf), _ptr(acc), _ptr(ph)))
+        return (acc, ph) if pot else acc
 
     def forces(self, acc=None, pot=False):
         torch = _torch()

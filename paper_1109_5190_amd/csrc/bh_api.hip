@@ -369,6 +369,7 @@ bh_status bh_rebuild(bh_ctx *ctx, bh_tree *t, const double *pos, const double *m
     t->pos = pos;
     t->mass = mass;
     t->upward_done = false;
+    t->lists_buf = nullptr;
     HIPCHK(launch_build(t->F.dev, pos, mass, ctx->stream));
     return BH_OK;
 }
@@ -377,6 +378,97 @@ bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
     HIPCHK(launch_upward(t->F.dev, ctx->stream));
     t->upward_done = true;
+    t->lists_buf = nullptr;
+    return BH_OK;
+}
+
+// ------------------------------------------------------ interaction lists ---
+
+namespace {
+
+struct ListLayout {
+    size_t head, count, next, ent, total;
+};
+
+size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+ListLayout list_layout(size_t ngroups, size_t nchunks) {
+    ListLayout l;
+    l.head = 256;
+    l.count = up256(l.head + 4 * ngroups);
+    l.next = up256(l.count + 4 * ngroups);
+    l.ent = up256(l.next + 4 * nchunks);
+    l.total = l.ent + sizeof(bh_list_entry) * 64 * nchunks;
+    return l;
+}
+
+// largest chunk count whose layout fits in `bytes`
+size_t list_chunks_for(size_t ngroups, size_t bytes) {
+    const size_t fixed = list_layout(ngroups, 0).total;
+    if (bytes <= fixed + 256) return 0;
+    size_t c = (bytes - fixed - 256) / (4 + sizeof(bh_list_entry) * 64);
+    while (c > 0 && list_layout(ngroups, c).total > bytes) --c;
+    return c > 0xffffffffu ? 0xffffffffu : c;
+}
+
+ListDev list_dev(void *buf, size_t ngroups, size_t nchunks) {
+    const ListLayout l = list_layout(ngroups, nchunks);
+    char *b = static_cast<char *>(buf);
+    ListDev d;
+    d.ctr = reinterpret_cast<unsigned long long *>(b);
+    d.head = reinterpret_cast<uint32_t *>(b + l.head);
+    d.count = reinterpret_cast<uint32_t *>(b + l.count);
+    d.next = reinterpret_cast<uint32_t *>(b + l.next);
+    d.ent = reinterpret_cast<uint4 *>(b + l.ent);
+    d.nchunks = (uint32_t)nchunks;
+    return d;
+}
+
+bh_status lists_supported(const bh_tree *t) {
+    for (const SegDesc &d : t->F.seg)
+        if (d.precision != BH_FP32 || d.quad || d.group)
+            return bh_fail(BH_E_INVAL, "interaction lists: FP32 trees with the monopole and the per-body test only");
+    return BH_OK;
+}
+
+}  // namespace
+
+static_assert(sizeof(bh_list_entry) == 16, "list entries are 16 bytes");
+
+bh_status bh_lists_build(bh_ctx *ctx, bh_tree *t, void *buf, size_t bytes, size_t *bytes_needed) {
+    if (!ctx || !t || !buf) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(buf) % 256) return bh_fail(BH_E_INVAL, "list buffer must be 256-byte aligned");
+    if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_lists_build");
+    bh_status st = lists_supported(t);
+    if (st != BH_OK) return st;
+    t->lists_buf = nullptr;
+    const size_t ng = t->F.dev.ngroups;
+    const size_t nc = list_chunks_for(ng, bytes);
+    if (nc == 0) {
+        if (bytes_needed) *bytes_needed = list_layout(ng, ng).total;
+        return bh_fail(BH_E_NOMEM, "list buffer too small");
+    }
+    const ListDev ld = list_dev(buf, ng, nc);
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ld.ctr), 0, 2, ctx->stream));
+    HIPCHK(launch_lists_build(t->F.dev, ld, ctx->stream));
+    unsigned long long taken = 0;
+    HIPCHK(hipMemcpyAsync(&taken, ld.ctr, sizeof(taken), hipMemcpyDeviceToHost, ctx->stream));
+    st = bh_forest_check_err(t->F);
+    if (st != BH_OK) return st;
+    const size_t need = list_layout(ng, taken).total;
+    if (bytes_needed) *bytes_needed = need;
+    if (taken > nc) return bh_fail(BH_E_NOMEM, "list buffer too small for these lists (see bytes_needed)");
+    t->lists_buf = buf;
+    t->lists_chunks = (uint32_t)nc;
+    return BH_OK;
+}
+
+bh_status bh_lists_forces(bh_ctx *ctx, bh_tree *t, const void *buf, double *acc, double *pot) {
+    if (!ctx || !t || !buf || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!t->lists_buf || t->lists_buf != buf)
+        return bh_fail(BH_E_INVAL, "no interaction lists of the current tree in this buffer");
+    const ListDev ld = list_dev(const_cast<void *>(buf), t->F.dev.ngroups, t->lists_chunks);
+    HIPCHK(launch_lists_eval(t->F.dev, ld, pot != nullptr, acc, pot, ctx->stream));
     return BH_OK;
 }
 

@@ -264,6 +264,17 @@ hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *ac
 // phase_mask 0: every simulation; else only those whose SegDesc.phase has a bit of the mask.
 hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s);
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);
+// Interaction lists of one forest (two-phase walk): entries (a, b, mask lo, mask hi) in
+// chunks of 64, chained per walk group.
+struct ListDev {
+    uint4 *ent;
+    uint32_t *head, *count, *next;   // per group: first chunk, entries; per chunk: next chunk
+    unsigned long long *ctr;         // chunks taken (beyond nchunks: counted, not written)
+    uint32_t nchunks;
+};
+hipError_t launch_lists_build(const ForestDev &f, const ListDev &ld, hipStream_t s);
+hipError_t launch_lists_eval(const ForestDev &f, const ListDev &ld, bool want_pot, double *acc, double *pot,
+                             hipStream_t s);
 hipError_t launch_kick_kick_drift(const ForestDev &f, double *pos, double *vel, const double *acc, hipStream_t s);
 hipError_t launch_energy(const ForestDev &f, const double *vel, const double *mass, const double *pot,
                          double *out2, hipStream_t s);

@@ -35,6 +35,8 @@ struct bh_tree {
     const double *pos = nullptr;
     const double *mass = nullptr;
     bool upward_done = false;
+    const void *lists_buf = nullptr;   // interaction lists of the current tree (bh_lists_build)
+    uint32_t lists_chunks = 0;
 };
 
 struct bh_sim {
