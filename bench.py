@@ -340,6 +340,28 @@ def main():
         b1.record(stream)
         torch.cuda.synchronize()
         ms_build = b0.elapsed_time(b1) / a.walk_reps
+        lists = None
+        if prec == "fp32":
+            # the two-phase form of the same walk: interaction lists written, then evaluated
+            buf = tree.lists_build()
+            tree.lists_forces(acc)
+            torch.cuda.synchronize()
+            l0, l1 = _events(torch)
+            l2, l3 = _events(torch)
+            l0.record(stream)
+            for _ in range(a.walk_reps):
+                tree.lists_build(reuse=True)
+            l1.record(stream)
+            torch.cuda.synchronize()
+            l2.record(stream)
+            for _ in range(a.walk_reps):
+                tree.lists_forces(acc)
+            l3.record(stream)
+            torch.cuda.synchronize()
+            nbytes = int(buf[:256 * 256].cpu().numpy().view(np.uint64)[::32].sum()) * 64 * 16
+            lists = {"build_ms": l0.elapsed_time(l1) / a.walk_reps, "eval_ms": l2.elapsed_time(l3) / a.walk_reps,
+                     "list_entry_bytes": nbytes, "bitwise_equal_to_walk": bool(torch.equal(acc, tree.forces()))}
+            del buf
         st = tree.forces_stats()
         torch.cuda.synchronize()
         tot = st["totals"]
@@ -348,7 +370,7 @@ def main():
                              interactions=inter, visits=int(tot["n_visits"]), fallbacks=int(tot["n_fallback"]),
                              wave_visits=int(tot["wave_visits"]), wave_entries=int(tot["wave_entries"]),
                              wave_accepts=int(tot["wave_accepts"]), wave_leaves=int(tot["wave_leaves"]),
-                             acc=st["acc"].cpu().numpy())
+                             acc=st["acc"].cpu().numpy(), lists=lists)
         print(f"# {prec}: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, build+upward {ms_build:.3f} ms, "
               f"{inter / a.n:.1f} interactions/particle", file=sys.stderr, flush=True)
         del sim, tree
@@ -386,6 +408,8 @@ def main():
                       "lane_utilisation": r["interactions"] / max(1, 64 * r["wave_visits"])},
         "build_upward_ms": r["ms_build_upward"],
     }
+    if r.get("lists"):
+        out["two_phase_lists"] = r["lists"]
     for prec, rr in results.items():
         if prec == head:
             continue

@@ -201,8 +201,11 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, 
  *                          preorder id), for the bodies in mask.
  * Buffer layout (device memory, 256-byte aligned, `bytes` long; G groups and
  * C chunks of 64 entries, C the largest count that fits):
- *   byte 0:                 uint64, chunks the last build took;
- *   byte 256:               uint32 head[G], first chunk of each group;
+ *   byte 256 k (k < 256):   uint64, chunks the last build reserved from
+ *                           partition k (chunk ids k, k + 256, k + 512, ...:
+ *                           group g takes its chunks from partition g mod 256,
+ *                           4 at a time; reserved chunks may stay unused);
+ *   byte 65536:             uint32 head[G], first chunk of each group;
  *   next 256-byte boundary: uint32 count[G], entries of each group;
  *   next 256-byte boundary: uint32 next[C], the group's next chunk
  *                           (0xffffffff: last);
@@ -216,7 +219,9 @@ typedef struct {
 
 /* Phase one.  SYNC.  *bytes_needed (nullable) receives the buffer size these
  * lists need; when it exceeds `bytes` the call returns BH_E_NOMEM and the
- * buffer holds no usable lists (call again with a larger buffer). */
+ * buffer holds no usable lists (call again with a buffer of that size).  If
+ * `bytes` cannot even hold the counters and group tables, nothing runs and
+ * *bytes_needed is only a lower bound. */
 bh_status bh_lists_build(bh_ctx *ctx, bh_tree *tree, void *buf, size_t bytes, size_t *bytes_needed);
 
 /* Phase two over the lists the last successful bh_lists_build of this tree

@@ -221,13 +221,16 @@ class Tree:
         _check(lib().bh_upward(self.ctx.h, self.h))
         return self
 
-    def lists_build(self, nbytes=None):
+    def lists_build(self, nbytes=None, reuse=False):
         """bh_lists_build into a torch-owned buffer (grown to the size the call reports if it is
-        too small).  Returns the buffer (uint8, 256-byte aligned view), kept for lists_forces."""
-        torch = _torch()
+        too small; reuse=True writes into the buffer of the last call).  Returns the buffer
+        (uint8, 256-byte aligned view), kept for lists_forces."""
         nbytes = int(nbytes or 4096 * (self.n // 64 + 1) * 16 + (1 << 20))
-        for _ in range(2):
-            raw, buf = workspace(nbytes, self.pos.device)
+        for attempt in range(2):
+            if reuse and attempt == 0 and getattr(self, "_lists", None):
+                raw, buf = self._lists
+            else:
+                raw, buf = workspace(nbytes, self.pos.device)
             need = C.c_size_t(0)
             st = lib().bh_lists_build(self.ctx.h, self.h, _ptr(buf), buf.numel(), C.byref(need))
             if st == OK:

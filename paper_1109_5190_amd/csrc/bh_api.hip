@@ -394,7 +394,7 @@ size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 ListLayout list_layout(size_t ngroups, size_t nchunks) {
     ListLayout l;
-    l.head = 256;
+    l.head = 256 * kListParts;
     l.count = up256(l.head + 4 * ngroups);
     l.next = up256(l.count + 4 * ngroups);
     l.ent = up256(l.next + 4 * nchunks);
@@ -402,7 +402,7 @@ ListLayout list_layout(size_t ngroups, size_t nchunks) {
     return l;
 }
 
-// largest chunk count whose layout fits in `bytes`
+// largest chunk count whose layout fits in `bytes` (0 also when not even the tables fit)
 size_t list_chunks_for(size_t ngroups, size_t bytes) {
     const size_t fixed = list_layout(ngroups, 0).total;
     if (bytes <= fixed + 256) return 0;
@@ -443,21 +443,30 @@ bh_status bh_lists_build(bh_ctx *ctx, bh_tree *t, void *buf, size_t bytes, size_
     if (st != BH_OK) return st;
     t->lists_buf = nullptr;
     const size_t ng = t->F.dev.ngroups;
-    const size_t nc = list_chunks_for(ng, bytes);
-    if (nc == 0) {
+    if (bytes < list_layout(ng, 0).total) {
+        // not even the counters and group tables fit: a lower bound (one chunk per group)
         if (bytes_needed) *bytes_needed = list_layout(ng, ng).total;
-        return bh_fail(BH_E_NOMEM, "list buffer too small");
+        return bh_fail(BH_E_NOMEM, "list buffer too small for its tables");
     }
+    const size_t nc = list_chunks_for(ng, bytes);   // may be 0: the walk then only counts
     const ListDev ld = list_dev(buf, ng, nc);
-    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ld.ctr), 0, 2, ctx->stream));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(ld.ctr), 0, 64 * kListParts, ctx->stream));
     HIPCHK(launch_lists_build(t->F.dev, ld, ctx->stream));
-    unsigned long long taken = 0;
-    HIPCHK(hipMemcpyAsync(&taken, ld.ctr, sizeof(taken), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<unsigned long long> taken(32 * kListParts);
+    HIPCHK(hipMemcpyAsync(taken.data(), ld.ctr, sizeof(unsigned long long) * taken.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
     st = bh_forest_check_err(t->F);
     if (st != BH_OK) return st;
-    const size_t need = list_layout(ng, taken).total;
+    // chunk ids of partition k are k + kListParts t: the lists need ids up to the largest one
+    // reserved (a wave reserves kListReserve at a time and may leave some unused)
+    size_t span = 0;
+    for (uint32_t k = 0; k < kListParts; ++k) {
+        const unsigned long long n = taken[32 * (size_t)k];
+        if (n) span = std::max<size_t>(span, (size_t)(n - 1) * kListParts + k + 1);
+    }
+    const size_t need = list_layout(ng, span).total;
     if (bytes_needed) *bytes_needed = need;
-    if (taken > nc) return bh_fail(BH_E_NOMEM, "list buffer too small for these lists (see bytes_needed)");
+    if (span > nc) return bh_fail(BH_E_NOMEM, "list buffer too small for these lists (see bytes_needed)");
     t->lists_buf = buf;
     t->lists_chunks = (uint32_t)nc;
     return BH_OK;

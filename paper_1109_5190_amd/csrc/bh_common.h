@@ -266,10 +266,13 @@ hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint3
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);
 // Interaction lists of one forest (two-phase walk): entries (a, b, mask lo, mask hi) in
 // chunks of 64, chained per walk group.
+constexpr uint32_t kListParts = 256;   // chunk counters; group g takes chunks g mod 256 + 256 t
+constexpr uint32_t kListReserve = 4;   // chunks a wave reserves per counter update
 struct ListDev {
     uint4 *ent;
     uint32_t *head, *count, *next;   // per group: first chunk, entries; per chunk: next chunk
-    unsigned long long *ctr;         // chunks taken (beyond nchunks: counted, not written)
+    unsigned long long *ctr;         // kListParts counters, 32 apart: chunks taken from each
+                                     // (beyond nchunks: counted, not written)
     uint32_t nchunks;
 };
 hipError_t launch_lists_build(const ForestDev &f, const ListDev &ld, hipStream_t s);

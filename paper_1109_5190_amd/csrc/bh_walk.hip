@@ -1074,10 +1074,8 @@ constexpr uint32_t kListNone = 0xffffffffu;    // end of a group's chunk chain
 template <int W>
 __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     __shared__ WaveLds32 lds_all[W];
-    __shared__ uint4 ebuf_all[W][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveLds32 &L = lds_all[wave];
-    uint4 *ebuf = ebuf_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;
@@ -1102,13 +1100,25 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     const float band2 = 16.0f * kU32 * kU32;
 
     uint32_t ne = 0, total = 0, prev = kListNone;   // wave-uniform
+    unsigned long long res = 0;                      // next reserved local chunk index
+    uint32_t nres = 0;                               // reserved chunks left
+    uint4 mine = make_uint4(0, 0, 0, 0);             // entry `lane` of the chunk being filled
     auto flush_chunk = [&]() {
-        wave_sync();
-        unsigned long long id = 0;
-        if (lane == 0) id = atomicAdd(ld.ctr, 1ull);
-        id = __shfl(id, 0, 64);
+        // group gi takes chunk ids part + kListParts t from the counter of part = gi mod
+        // kListParts (counters on separate 256-byte lines), kListReserve at a time, so that few
+        // waves meet on one address
+        const uint32_t part = gi % kListParts;
+        if (nres == 0) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(ld.ctr + (size_t)part * 32, (unsigned long long)kListReserve);
+            res = __shfl(base, 0, 64);
+            nres = kListReserve;
+        }
+        const unsigned long long id = res * kListParts + part;
+        ++res;
+        --nres;
         if (id < ld.nchunks) {
-            if ((uint32_t)lane < ne) ld.ent[id * 64 + lane] = ebuf[lane];
+            if ((uint32_t)lane < ne) ld.ent[id * 64 + lane] = mine;
             if (lane == 0) {
                 if (prev == kListNone) ld.head[gi] = (uint32_t)id;
                 else ld.next[prev] = (uint32_t)id;
@@ -1118,10 +1128,10 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
         prev = id < ld.nchunks ? (uint32_t)id : kListNone;
         total += ne;
         ne = 0;
-        wave_sync();
     };
+    // the chunk being filled lives in registers: entry k in lane k
     auto emit = [&](uint32_t a, uint32_t b, uint64_t m) {
-        if (lane == 0) ebuf[ne] = make_uint4(a, b, (uint32_t)m, (uint32_t)(m >> 32));
+        if ((uint32_t)lane == ne) mine = make_uint4(a, b, (uint32_t)m, (uint32_t)(m >> 32));
         if (++ne == 64) flush_chunk();
     };
 
@@ -1150,7 +1160,9 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
         }
         wave_sync();
         emit(kListEntry, nch, 0);
-        for (uint32_t c = 0; c < nch; ++c) {
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
             const float4 qa = L.sa[c];
             const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
             const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
@@ -1197,8 +1209,10 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
 template <bool POT, bool SOFT, int W>
 __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld, WalkOut out) {
     __shared__ WaveLds32 lds_all[W];
+    __shared__ float4 mst_all[W][64];   // accepted cubes of the current chunk: centre rel g, mass
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveLds32 &L = lds_all[wave];
+    float4 *mst = mst_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & (kErrTree | kErrStack)) return;
@@ -1310,6 +1324,14 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
     for (uint32_t k0 = 0; k0 < n; k0 += 64) {
         const uint32_t nb = n - k0 < 64u ? n - k0 : 64u;
         const uint4 mine = (uint32_t)lane < nb ? ld.ent[(size_t)chunk * 64 + lane] : make_uint4(0, 0, 0, 0);
+        // the chunk's accepted cubes, converted lane-parallel as the walk stages children
+        wave_sync();
+        if ((uint32_t)lane < nb && mine.x != kListEntry && !(mine.y & kListLeaf)) {
+            const WRec32 &w = f.w32[mine.x];
+            mst[lane] = make_float4((float)__dsub_rn(w.cx, gx), (float)__dsub_rn(w.cy, gy),
+                                    (float)__dsub_rn(w.cz, gz), w.m);
+        }
+        wave_sync();
         for (uint32_t k = 0; k < nb; ++k) {
             const uint32_t a = (uint32_t)__builtin_amdgcn_readlane(mine.x, k);
             const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(mine.y, k);
@@ -1340,14 +1362,11 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
                     }
                 }
             } else if (in_mask(m)) {
-                const WRec32 &w = f.w32[a];
-                const float qx = (float)__dsub_rn(w.cx, gx);
-                const float qy = (float)__dsub_rn(w.cy, gy);
-                const float qz = (float)__dsub_rn(w.cz, gz);
-                const float dx = qx - tx, dy = qy - ty, dz = qz - tz;
+                const float4 qa = mst[k];
+                const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
                 const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
                 const float ri = __builtin_amdgcn_rsqf(E2);
-                const float mr = w.m * ri;
+                const float mr = qa.w * ri;
                 const float ri2 = ri * ri;
                 const float w3 = mr * ri2;
                 ax = fmaf(w3, dx, ax);

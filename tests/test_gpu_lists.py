@@ -68,7 +68,7 @@ def up256(v):
 
 
 def layout(G, Cn):
-    head = 256
+    head = 256 * 256
     count = up256(head + 4 * G)
     nxt = up256(count + 4 * G)
     ent = up256(nxt + 4 * Cn)
@@ -157,7 +157,7 @@ def test_buffer_sizing_and_validity(ctx):
     t = bh.Tree(ctx, pos, mass, bh.params(0.5, 0.01, precision="fp32")).upward()
     with pytest.raises(bh.BHError):
         t.lists_forces()                       # nothing built yet
-    raw, small = bh.workspace(64 * 1024, pos.device)
+    raw, small = bh.workspace(256 * 1024, pos.device)   # the tables fit, the lists do not
     need = C.c_size_t(0)
     st = bh.lib().bh_lists_build(ctx.h, t.h, C.c_void_p(small.data_ptr()), small.numel(), C.byref(need))
     assert st == bh.E_NOMEM and need.value > small.numel()
