@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--leaf-cap", type=int, default=1)
     ap.add_argument("--walk-reps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=262144, help="oracle walk targets for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=524288, help="oracle walk targets for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="fp32,fp64")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg (0: skip)")
