@@ -433,22 +433,23 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
 
 // ------------------------------------------------------------- FP64 walk ---
 
+template <bool QUAD>
 struct WaveLds64 {
     uint4 stk[kStackMax];
-    double4 sa[8];         // child: centre of mass, mass
-    double sS[8];          // child: side^2
-    uint4 sb[8];           // child: link, cnt, gid, level
-    double sq[8 * 6];      // child (quadrupole walks): second moments (xx yy zz xy xz yz)
-    uint32_t irank[64];
-    uint64_t imask[64];
-    double4 pst[64];
+    double4 sa[8];              // child: centre of mass, mass
+    double sS[8];               // child: r^2 of the opening test
+    uint4 sb[8];                // child: link, cnt, gid, level
+    double sq[QUAD ? 8 * 6 : 1];// child (quadrupole walks): second moments (xx yy zz xy xz yz)
+    uint32_t irank[64];         // queued leaf particles: rank
+    uint64_t imask[64];         //                        lane mask
+    double4 pst[32];            //                        position, mass (32 at a time)
 };
 
 template <bool STATS, bool POT, int W, bool QUAD>
 __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
-    __shared__ WaveLds64 lds_all[W];
+    __shared__ WaveLds64<QUAD> lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    WaveLds64 &L = lds_all[wave];
+    WaveLds64<QUAD> &L = lds_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
     if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
@@ -484,21 +485,24 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     };
     auto flush_leaves = [&]() {
         if (qn == 0) return;
-        wave_sync();
-        if ((uint32_t)lane < qn) {
-            const size_t j = L.irank[lane];
-            L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
-        }
-        wave_sync();
-        for (uint32_t k = 0; k < qn; ++k) {
-            const uint32_t jq = uni(L.irank[k]);
-            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
-            if (in_mask(m)) {
-                const double4 p = L.pst[k];
-                pair(p.x, p.y, p.z, p.w);
-                if (STATS) {
-                    ++np2p;
-                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+            wave_sync();
+            if ((uint32_t)lane < nb) {
+                const size_t j = L.irank[k0 + lane];
+                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+            }
+            wave_sync();
+            for (uint32_t k = 0; k < nb; ++k) {
+                const uint32_t jq = uni(L.irank[k0 + k]);
+                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                if (in_mask(m)) {
+                    const double4 p = L.pst[k];
+                    pair(p.x, p.y, p.z, p.w);
+                    if (STATS) {
+                        ++np2p;
+                        h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                    }
                 }
             }
         }
