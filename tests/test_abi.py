@@ -95,3 +95,20 @@ def test_context_without_device_reports_error(bh):
     st = L.bh_ctx_create(0, None, C.byref(h))
     assert st in (bh.E_DEVICE, bh.E_INVAL)
     assert L.bh_last_error()
+
+
+@pytest.mark.parametrize("flags", [2 | 4, 8 | 16, 8 | 4, 16 | 4, 1 << 7, 1 << 31])
+def test_flag_combinations_rejected_on_the_host(bh, flags):
+    """Options that exclude each other (quadrupole and group criterion; the two opening radii;
+    a radius other than the side with the group criterion) and unknown bits are refused by the
+    host-side parameter check, without a device."""
+    p = bh.params(0.5, 0.01)
+    p.flags = flags
+    assert bh.lib().bh_workspace_bytes(1000, C.byref(p)) == 0
+
+
+@pytest.mark.parametrize("flags", [0, 2, 4, 8, 16, 2 | 8, 2 | 16, 1])
+def test_flag_combinations_accepted_on_the_host(bh, flags):
+    p = bh.params(0.5, 0.01)
+    p.flags = flags
+    assert bh.lib().bh_workspace_bytes(1000, C.byref(p)) > 0
