@@ -164,8 +164,6 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.uS = c.take<double>(3 * Mc);
     D.rlam = c.take<uint8_t>(N);
     D.tile_mm = c.take<unsigned long long>(6 * (size_t)cap.ntiles);
-    D.nM = c.take<double>(Mc);
-    D.nS = c.take<double>(3 * Mc);
     D.w32 = cap.fp32 ? c.take<WRec32>(Mc) : nullptr;
     D.w64 = cap.fp64 ? c.take<WRec64>(Mc) : nullptr;
     D.uQ = cap.quad ? c.take<double>(6 * (size_t)Mc) : nullptr;

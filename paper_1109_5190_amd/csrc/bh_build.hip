@@ -851,11 +851,7 @@ __global__ void k_records(ForestDev f) {
     }
     const double M = f.uM[sl];
     double c[3];
-    for (int d = 0; d < 3; ++d) {
-        c[d] = f.uS[3 * (size_t)sl + d] / M;
-        f.nS[3 * (size_t)g + d] = c[d];
-    }
-    f.nM[g] = M;
+    for (int d = 0; d < 3; ++d) c[d] = f.uS[3 * (size_t)sl + d] / M;
     const uint32_t sid = f.segid[f.nfirst[g]];
     const SegDesc &sd = f.seg[sid];
     const SegState &st = f.st[sid];
@@ -963,9 +959,11 @@ __global__ void k_export_nodes(ForestDev f, uint32_t seg, int32_t *level, uint32
     if (first) first[j] = f.nfirst[g] - sd.start;
     if (count) count[j] = f.ncount[g];
     if (parent) parent[j] = f.nparent[g] == kNone ? -1 : (int32_t)(f.nparent[g] - st.nbase);
-    if (M) M[j] = f.nM[g];
+    // mass and centre of mass by walk slot, the centre divided exactly as the records do
+    const uint32_t sl = f.slot_of[g];
+    if (M) M[j] = f.uM[sl];
     if (com)
-        for (int d = 0; d < 3; ++d) com[3 * (size_t)j + d] = f.nS[3 * (size_t)g + d];
+        for (int d = 0; d < 3; ++d) com[3 * (size_t)j + d] = f.uS[3 * (size_t)sl + d] / f.uM[sl];
 }
 
 hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,

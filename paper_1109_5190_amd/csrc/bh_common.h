@@ -114,7 +114,6 @@ struct ForestDev {
     double *q64;                // FP64 walk: second moments by slot (xx yy zz xy xz yz)
     uint8_t *rlam;              // per row that starts a leaf: the leaf's level
     unsigned long long *tile_mm; // per tile: integer images of the bbox min (3) and max (3)
-    double *nM, *nS;            // node mass, centre of mass (FP64; S then com in place)
     WRec32 *w32;
     WRec64 *w64;
     uint32_t *err;              // device error word

@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                     // within the FP32 rounding bound of the threshold: decide exactly in FP64
                     bool ex = false;
                     if (in_mask(ambm)) {
-                        const uint2 qc = L.sc[c];
-                        const double *cm = f.nS + 3 * (size_t)qc.x;
+                        const WRec32 &wc = f.w32[link + c];
+                        const double cm[3] = {wc.cx, wc.cy, wc.cz};
                         const double *xp = f.spos + 3 * (size_t)r;
                         const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
                                      ez = __dsub_rn(cm[2], xp[2]);
@@ -360,8 +360,8 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                     const uint64_t hard = ballot(s1.z > qa.w * E2) & accm;
                     if (hard) {
                         if (in_mask(hard)) {
-                            const uint2 qc = L.sc[c];
-                            const double *cm = f.nS + 3 * (size_t)qc.x;
+                            const WRec32 &wc = f.w32[link + c];
+                            const double cm[3] = {wc.cx, wc.cy, wc.cz};
                             const double *xp = f.spos + 3 * (size_t)r;
                             const double *S = f.uQ + 6 * (size_t)(link + c);
                             const double ex_ = cm[0] - xp[0], ey = cm[1] - xp[1], ez = cm[2] - xp[2];
@@ -1177,8 +1177,8 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
                 if (ambm) {
                     bool ex = false;
                     if (in_mask(ambm)) {
-                        const uint2 qc = L.sc[c];
-                        const double *cm = f.nS + 3 * (size_t)qc.x;
+                        const WRec32 &wc = f.w32[link + c];
+                        const double cm[3] = {wc.cx, wc.cy, wc.cz};
                         const double *xp = f.spos + 3 * (size_t)r;
                         const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
                                      ez = __dsub_rn(cm[2], xp[2]);
