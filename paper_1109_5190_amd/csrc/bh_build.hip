@@ -548,6 +548,17 @@ __global__ void __launch_bounds__(256) k_mark(ForestDev f) {
 
 constexpr uint32_t kInner = 0xFFFFFFFFu;   // nchild of an internal node until its children are linked
 
+// Node tables before the fill pass: no children, no parent, no rank (every id
+// below the node count is then written by k_fill or k_link; the rest stays
+// clear for the child-count scan over the capacity).
+__global__ void k_clear_nodes(ForestDev f) {
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < f.mcap; g += (size_t)gridDim.x * blockDim.x) {
+        f.nchild[g] = 0;
+        f.nparent[g] = kNone;
+        f.ncrank[g] = kNone;
+    }
+}
+
 // Fill pass: node records (level, first rows, count) at their preorder ids.
 __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -636,7 +647,12 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
         const uint32_t rk = f.ncrank[g];
         uint32_t sl = kNone;
         if (p == kNone) {
-            if (rk < f.nseg) sl = rk;
+            if (rk < f.nseg) {
+                sl = rk;
+                // the simulation's node count, from its root
+                const SegDesc &sd = f.seg[rk];
+                f.st[rk].nn = f.base[sd.start + sd.n] - f.base[sd.start];
+            }
         } else if (p < mtot && rk < 8) {
             sl = f.nseg + f.cs[p] + rk;
         }
@@ -668,15 +684,8 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
     if (lvl >= 0) f.lvl_list[(size_t)blockIdx.x * blockDim.x + start[lvl] + rank] = entry;
 }
 
-__global__ void k_seg_nodes(ForestDev f) {
-    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= f.nseg) return;
-    const SegDesc &sd = f.seg[s];
-    f.st[s].nn = f.base[sd.start + sd.n] - f.base[sd.start];
-}
 
 hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass, hipStream_t s) {
-    const unsigned segb = (f.nseg + 255) / 256;
     hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
     hipLaunchKernelGGL(k_bbox_reduce, dim3(f.nseg), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
@@ -697,19 +706,17 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
     hipLaunchKernelGGL(k_mark, dim3(nb), dim3(256), 0, s, f);
     hipError_t e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(f.nchild, 0, f.mcap, s);
-    if (e != hipSuccess) return e;
-    e = launch_fill_u32(f.nparent, kNone, f.mcap, s);
-    if (e != hipSuccess) return e;
-    e = launch_fill_u32(f.ncrank, kNone, f.mcap, s);
-    if (e != hipSuccess) return e;
+    {
+        unsigned fb = (f.mcap + 255) / 256;
+        if (fb > 4096) fb = 4096;
+        hipLaunchKernelGGL(k_clear_nodes, dim3(fb), dim3(256), 0, s, f);
+    }
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, f);
     const unsigned mb = (f.mcap + 255) / 256;
     hipLaunchKernelGGL(k_link, dim3(mb), dim3(256), 0, s, f);
     e = scan_exclusive(f.nchild, f.mcap, f.cs, f.scan_tmp, 0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_slots, dim3(mb), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_seg_nodes, dim3(segb), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 
