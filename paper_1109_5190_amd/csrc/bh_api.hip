@@ -147,6 +147,7 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     D.scan_tmp = c.take<uint32_t>(scan_len / 2048 + 2);
     D.spos = c.take<double>(3 * N);
     D.smass = c.take<double>(N);
+    D.pk = c.take<double4>(N);
     D.lcp = c.take<int8_t>(N + 1);
     D.mask = c.take<uint32_t>(N);
     D.base = c.take<uint32_t>(N + 1);

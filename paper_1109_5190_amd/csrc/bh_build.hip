@@ -184,20 +184,24 @@ hipError_t launch_segid(const ForestDev &f, hipStream_t s) {
 
 // =================================================================== bbox ===
 
-__global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos) {
+__global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos, const double *mass) {
     const TileDesc td = f.tiles[blockIdx.x];
     const SegDesc &sd = f.seg[td.seg];
     const double *pb = seg_base(pos, sd.pos, sd, 3);
+    const double *mb = seg_base(mass, sd.mass, sd, 1);
     const uint32_t j0 = td.start - sd.start;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
         size_t i = (size_t)j0 + j;
+        double v[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double v = pb[3 * i + d];
-            mn[d] = fmin(mn[d], v);
-            mx[d] = fmax(mx[d], v);
+            v[d] = pb[3 * i + d];
+            mn[d] = fmin(mn[d], v[d]);
+            mx[d] = fmax(mx[d], v[d]);
         }
+        // the particle as one aligned record, for the gather into key order
+        f.pk[(size_t)td.start + j] = make_double4(v[0], v[1], v[2], mb[i]);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -438,19 +442,20 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, cons
 
 // ================================================================ permute ===
 
-__global__ void k_permute(ForestDev f, const double *pos, const double *mass) {
+__global__ void k_permute(ForestDev f) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= f.ntot) return;
     const SegDesc &sd = f.seg[f.segid[r]];
     const size_t li = f.idx[r] - sd.start;
-    const double *pb = seg_base(pos, sd.pos, sd, 3);
-    const double *mb = seg_base(mass, sd.mass, sd, 1);
-    double x = pb[3 * li], y = pb[3 * li + 1], z = pb[3 * li + 2];
-    double m = mb[li];
-    f.spos[3 * (size_t)r] = x;
-    f.spos[3 * (size_t)r + 1] = y;
-    f.spos[3 * (size_t)r + 2] = z;
-    f.smass[r] = m;
+    if (li >= sd.n) {   // cannot happen after a correct sort
+        atomicOr(f.err, kErrTree);
+        return;
+    }
+    const double4 p = f.pk[sd.start + li];
+    f.spos[3 * (size_t)r] = p.x;
+    f.spos[3 * (size_t)r + 1] = p.y;
+    f.spos[3 * (size_t)r + 2] = p.z;
+    f.smass[r] = p.w;
 }
 
 // ==================================================================== lcp ===
@@ -686,7 +691,7 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
 
 
 hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass, hipStream_t s) {
-    hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
+    hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos, mass);
     hipLaunchKernelGGL(k_bbox_reduce, dim3(f.nseg), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
     // 8 stable passes of 8 bits: the result returns to (keys, idx)
@@ -701,7 +706,7 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
     const unsigned nb = (f.ntot + 255) / 256;
-    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, s, f, pos, mass);
+    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_lcp, dim3((f.ntot + 1 + 255) / 256), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_mark, dim3(nb), dim3(256), 0, s, f);
     hipError_t e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);

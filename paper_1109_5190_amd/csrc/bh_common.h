@@ -97,6 +97,8 @@ struct ForestDev {
     uint32_t *segtot, *segp;    // sort: per simulation and digit, total and scan base
     uint32_t *scan_tmp;         // block sums of the scans
     double *spos, *smass;       // sorted state (FP64)
+    double4 *pk;                // per row in the caller's order: (x, y, z, m), one aligned 32-byte
+                                // record for the permute's gather
     int8_t *lcp;                // common-prefix level of neighbouring keys, -1 at segment edges
     uint32_t *mask;             // per row: bit l set if a node of level l starts at this row
     uint32_t *base;             // exclusive scan of popcount(mask): global node id base
