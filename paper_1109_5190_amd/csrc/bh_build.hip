@@ -941,7 +941,7 @@ hipError_t launch_upward(const ForestDev &f, hipStream_t s) {
     hipLaunchKernelGGL(k_up_leaf, dim3(mb), dim3(256), 0, s, f);
     // one wavefront per list block; the lists cover the node ids [0, mcap) in blocks of 256
     const unsigned nblk = mb;
-    const unsigned lb = (nblk + 3) / 4 < 1024 ? (nblk + 3) / 4 : 1024;
+    const unsigned lb = (nblk + 3) / 4;   // one wavefront per list block
     for (int l = kMaxLevel - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_up_level, dim3(lb), dim3(256), 0, s, f, l, nblk);
     hipLaunchKernelGGL(k_records, dim3(mb), dim3(256), 0, s, f);
