@@ -34,7 +34,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Inclusive scan of one value per thread over a 256-thread block.
+// Inclusive scan of one value per thread over the block (any multiple of 64
+// threads; lds_waves holds one entry per wavefront).
 __device__ inline uint32_t block_inclusive_scan_256(uint32_t v, uint32_t *lds_waves /*4*/) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -316,24 +317,40 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dig, uint64_t valid) {
 }
 
 
-__global__ void __launch_bounds__(kTileThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
-    __shared__ uint32_t hist[4][256];
+// The sort kernels give a tile 1024 threads (16 wavefronts of 4 keys each), so
+// that enough loads are in flight for one 4096-key tile per compute unit.
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = kTile / kSortThreads;
+
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
+    __shared__ uint32_t hist[kSortWaves][256];
     const TileDesc td = f.tiles[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = lane; d < 256; d += 64) hist[wave][d] = 0;
     __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
-#pragma unroll 4
-    for (int j = 0; j < kItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
-        bool valid = e < td.count;
-        uint32_t dig = valid ? (uint32_t)(keys[(size_t)td.start + e] >> shift) & 255u : 0u;
-        uint64_t peers = match_digit(dig, __ballot(valid));
-        if (valid && (peers & lt) == 0) hist[wave][dig] += (uint32_t)__popcll(peers);
+    uint32_t dg[kSortItems];
+    bool ok[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
+        ok[j] = e < td.count;
+        dg[j] = ok[j] ? (uint32_t)(keys[(size_t)td.start + e] >> shift) & 255u : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint64_t peers = match_digit(dg[j], __ballot(ok[j]));
+        if (ok[j] && (peers & lt) == 0) hist[wave][dg[j]] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    const uint32_t d = threadIdx.x;
-    f.cnt[256u * blockIdx.x + d] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+    if (threadIdx.x < 256) {
+        const uint32_t d = threadIdx.x;
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) t += hist[w][d];
+        f.cnt[256u * blockIdx.x + d] = t;
+    }
 }
 
 // Digit d (one block per digit): exclusive scan of the tile counts over the tiles of
@@ -368,33 +385,33 @@ __global__ void __launch_bounds__(256) k_sort_colscan(ForestDev f) {
     }
 }
 
-__global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
                                                                uint64_t *kout, uint32_t *iout, int shift) {
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sidx[kTile];
-    __shared__ uint32_t whist[4][256];
+    __shared__ uint32_t whist[kSortWaves][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t wtot[4];
+    __shared__ uint32_t wtot[kSortWaves];
     const TileDesc td = f.tiles[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
     for (int d = lane; d < 256; d += 64) whist[wave][d] = 0;
     __syncthreads();
 
-    uint64_t key[kItems];
-    uint32_t idv[kItems];
-    uint32_t rank[kItems];
+    uint64_t key[kSortItems];
+    uint32_t idv[kSortItems];
+    uint32_t rank[kSortItems];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < kSortItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
         bool valid = e < td.count;
         key[j] = valid ? kin[(size_t)td.start + e] : 0ull;
         idv[j] = valid ? iin[(size_t)td.start + e] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < kSortItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
         bool valid = e < td.count;
         uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
         uint64_t peers = match_digit(dig, __ballot(valid));
@@ -403,26 +420,38 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, cons
         if (valid && (peers & lt) == 0) whist[wave][dig] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit: offsets of the waves, tile-local start, global base
+    // per digit (threads 0..255): offsets of the waves, tile-local start, global base; every
+    // thread takes part in the block scans (the others with 0, after all digits)
     {
-        uint32_t d = threadIdx.x;
-        uint32_t c0 = whist[0][d], c1 = whist[1][d], c2 = whist[2][d], c3 = whist[3][d];
-        uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t inc = block_inclusive_scan_256(tot, wtot);
-        lstart[d] = inc - tot;
-        whist[0][d] = 0;
-        whist[1][d] = c0;
-        whist[2][d] = c0 + c1;
-        whist[3][d] = c0 + c1 + c2;
+        const uint32_t d = threadIdx.x;
+        uint32_t tot = 0;
+        uint32_t c[kSortWaves];
+        if (d < 256) {
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                c[w] = whist[w][d];
+                tot += c[w];
+            }
+        }
+        const uint32_t inc = block_inclusive_scan_256(tot, wtot);
         const SegDesc &sd = f.seg[td.seg];
-        const uint32_t tot_d = f.segtot[256u * td.seg + d];
+        const uint32_t tot_d = d < 256 ? f.segtot[256u * td.seg + d] : 0u;
         const uint32_t dinc = block_inclusive_scan_256(tot_d, wtot);
-        gbase[d] = sd.start + (dinc - tot_d) + f.cnt[256u * blockIdx.x + d];
+        if (d < 256) {
+            lstart[d] = inc - tot;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                whist[w][d] = run;
+                run += c[w];
+            }
+            gbase[d] = sd.start + (dinc - tot_d) + f.cnt[256u * blockIdx.x + d];
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < kSortItems; ++j) {
+        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
         if (e < td.count) {
             uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
             uint32_t p = lstart[dig] + whist[wave][dig] + rank[j];
@@ -431,7 +460,7 @@ __global__ void __launch_bounds__(kTileThreads) k_sort_scatter(ForestDev f, cons
         }
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < td.count; q += kTileThreads) {
+    for (uint32_t q = threadIdx.x; q < td.count; q += kSortThreads) {
         uint64_t k = skey[q];
         uint32_t dig = (uint32_t)(k >> shift) & 255u;
         uint32_t o = gbase[dig] + (q - lstart[dig]);
@@ -699,9 +728,9 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
     uint32_t *iin = f.idx, *iout = f.idx_alt;
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, shift);
+        hipLaunchKernelGGL(k_sort_hist, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, kin, shift);
         hipLaunchKernelGGL(k_sort_colscan, dim3(256), dim3(256), 0, s, f);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, kin, iin, kout, iout, shift);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, kin, iin, kout, iout, shift);
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
