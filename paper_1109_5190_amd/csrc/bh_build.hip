@@ -34,6 +34,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The per-tile streaming kernels (bbox, keys, sort histogram and scatter) give
+// a 4096-particle tile 1024 threads (16 wavefronts, 4 particles each), so that
+// enough loads are in flight with one tile per compute unit.
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = kTile / kSortThreads;
+
 // Inclusive scan of one value per thread over the block (any multiple of 64
 // threads; lds_waves holds one entry per wavefront).
 __device__ inline uint32_t block_inclusive_scan_256(uint32_t v, uint32_t *lds_waves /*4*/) {
@@ -185,14 +192,14 @@ hipError_t launch_segid(const ForestDev &f, hipStream_t s) {
 
 // =================================================================== bbox ===
 
-__global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double *pos, const double *mass) {
+__global__ void __launch_bounds__(kSortThreads) k_bbox(ForestDev f, const double *pos, const double *mass) {
     const TileDesc td = f.tiles[blockIdx.x];
     const SegDesc &sd = f.seg[td.seg];
     const double *pb = seg_base(pos, sd.pos, sd, 3);
     const double *mb = seg_base(mass, sd.mass, sd, 1);
     const uint32_t j0 = td.start - sd.start;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
+    for (uint32_t j = threadIdx.x; j < td.count; j += kSortThreads) {
         size_t i = (size_t)j0 + j;
         double v[3];
 #pragma unroll
@@ -211,15 +218,18 @@ __global__ void __launch_bounds__(kTileThreads) k_bbox(ForestDev f, const double
             mx[d] = fmax(mx[d], __shfl_xor(mx[d], o, 64));
         }
     }
-    __shared__ double wmn[4][3], wmx[4][3];
+    __shared__ double wmn[kSortWaves][3], wmx[kSortWaves][3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0)
         for (int d = 0; d < 3; ++d) { wmn[wave][d] = mn[d]; wmx[wave][d] = mx[d]; }
     __syncthreads();
     if (threadIdx.x < 3) {
         const int d = threadIdx.x;
-        double a = fmin(fmin(wmn[0][d], wmn[1][d]), fmin(wmn[2][d], wmn[3][d]));
-        double b = fmax(fmax(wmx[0][d], wmx[1][d]), fmax(wmx[2][d], wmx[3][d]));
+        double a = wmn[0][d], b = wmx[0][d];
+        for (int w = 1; w < kSortWaves; ++w) {
+            a = fmin(a, wmn[w][d]);
+            b = fmax(b, wmx[w][d]);
+        }
         f.tile_mm[6 * (size_t)blockIdx.x + d] = ord_enc(a);
         f.tile_mm[6 * (size_t)blockIdx.x + 3 + d] = ord_enc(b);
     }
@@ -258,7 +268,7 @@ __global__ void __launch_bounds__(256) k_bbox_reduce(ForestDev f) {
 // =================================================================== keys ===
 // q_d = floor(fl(x_d - lo_d) * 2^(21-k)); key = interleave with x the MSB of each digit.
 
-__global__ void __launch_bounds__(kTileThreads) k_keys(ForestDev f, const double *pos) {
+__global__ void __launch_bounds__(kSortThreads) k_keys(ForestDev f, const double *pos) {
     const TileDesc td = f.tiles[blockIdx.x];
     __shared__ double lo_s[3], scale_s;
     if (threadIdx.x == 0) {
@@ -288,7 +298,7 @@ __global__ void __launch_bounds__(kTileThreads) k_keys(ForestDev f, const double
     const SegDesc &sd = f.seg[td.seg];
     const double *pb = seg_base(pos, sd.pos, sd, 3);
     const uint32_t j0 = td.start - sd.start;
-    for (uint32_t j = threadIdx.x; j < td.count; j += kTileThreads) {
+    for (uint32_t j = threadIdx.x; j < td.count; j += kSortThreads) {
         size_t i = (size_t)td.start + j;
         uint64_t q[3];
 #pragma unroll
@@ -317,11 +327,6 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dig, uint64_t valid) {
 }
 
 
-// The sort kernels give a tile 1024 threads (16 wavefronts of 4 keys each), so
-// that enough loads are in flight for one 4096-key tile per compute unit.
-constexpr int kSortThreads = 1024;
-constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = kTile / kSortThreads;
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
     __shared__ uint32_t hist[kSortWaves][256];
@@ -720,9 +725,9 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
 
 
 hipError_t launch_build(const ForestDev &f, const double *pos, const double *mass, hipStream_t s) {
-    hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos, mass);
+    hipLaunchKernelGGL(k_bbox, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, pos, mass);
     hipLaunchKernelGGL(k_bbox_reduce, dim3(f.nseg), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kTileThreads), 0, s, f, pos);
+    hipLaunchKernelGGL(k_keys, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, pos);
     // 8 stable passes of 8 bits: the result returns to (keys, idx)
     uint64_t *kin = f.keys, *kout = f.keys_alt;
     uint32_t *iin = f.idx, *iout = f.idx_alt;

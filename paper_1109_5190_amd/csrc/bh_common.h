@@ -8,8 +8,6 @@ namespace bh {
 
 constexpr int kMaxLevel = 21;          // 63-bit Morton keys: 21 octant digits
 constexpr int kTile = 4096;            // particles per sort / bbox tile
-constexpr int kTileThreads = 256;
-constexpr int kItems = kTile / kTileThreads;   // 16 keys per thread in the sort
 constexpr int kGroup = 64;             // walk targets per wavefront
 constexpr int kWalkWaves[4] = {1, 2, 4, 8};   // walk launch shapes: wavefronts per block
 constexpr int kStackMax = 160;         // >= 1 + 7 * 21 entries of (child block, lane mask)
