@@ -147,3 +147,34 @@ def test_served_request_matches_oracle(ctx):
     x, v, a, _ = oracle.kdk(s.pos, s.vel, s.mass, 1e-3, 3, theta=0.5, eps=0.01)
     assert np.abs(pos.cpu().numpy() - x).max() <= 1e-10
     assert np.abs(vel.cpu().numpy() - v).max() <= 1e-9
+
+
+@pytest.mark.parametrize("variant", ["quadrupole", "bmax", "offset", "group"])
+def test_plummer_1m_variants_sampled(ctx, plummer_1m, variant):
+    """The headline sphere with each option of the opening test or expansion, both precisions,
+    1024 sampled targets against the oracle's walk with the same option."""
+    s, T = plummer_1m
+    rng = np.random.default_rng(14)
+    targets = np.sort(rng.choice(s.n, 1024, replace=False)).astype(np.int64)
+    if variant == "group":
+        ref = T.walk_group(0.5, 0.005, 1.0, 64, targets, nthreads=CORES)
+    else:
+        ref = T.walk(0.5, 0.005, 1.0, targets, nthreads=CORES, quad=variant == "quadrupole",
+                     open=variant if variant in ("bmax", "offset") else "side")
+    idx = torch.tensor(targets, device="cuda")
+    for prec in ("fp32", "fp64"):
+        print(f"[1m] {variant} {prec}", flush=True)
+        p = bh.params(0.5, 0.005, precision=prec, quad=variant == "quadrupole", group=variant == "group",
+                      open=variant if variant in ("bmax", "offset") else "side")
+        t = bh.Tree(ctx, dev(s.pos), dev(s.mass), p).upward()
+        r = t.forces_stats()
+        assert np.array_equal(r["n_mono"][idx].cpu().numpy(), ref["n_mono"])
+        assert np.array_equal(r["n_p2p"][idx].cpu().numpy(), ref["n_p2p"])
+        assert np.array_equal(u64(r["hash"][idx]), ref["hash"])
+        acc = r["acc"][idx].cpu().numpy()
+        if prec == "fp64":
+            assert rel_rms(acc, ref["acc"]) <= 1e-10
+        else:
+            assert rel_rms(acc, ref["acc"]) <= 2e-6
+            assert rel_max(acc, ref["acc"]) <= 1e-4
+        del t, r
