@@ -340,28 +340,26 @@ def main():
         b1.record(stream)
         torch.cuda.synchronize()
         ms_build = b0.elapsed_time(b1) / a.walk_reps
-        lists = None
-        if prec == "fp32":
-            # the two-phase form of the same walk: interaction lists written, then evaluated
-            buf = tree.lists_build()
+        # the two-phase form of the same walk: interaction lists written, then evaluated
+        buf = tree.lists_build()
+        tree.lists_forces(acc)
+        torch.cuda.synchronize()
+        l0, l1 = _events(torch)
+        l2, l3 = _events(torch)
+        l0.record(stream)
+        for _ in range(a.walk_reps):
+            tree.lists_build(reuse=True)
+        l1.record(stream)
+        torch.cuda.synchronize()
+        l2.record(stream)
+        for _ in range(a.walk_reps):
             tree.lists_forces(acc)
-            torch.cuda.synchronize()
-            l0, l1 = _events(torch)
-            l2, l3 = _events(torch)
-            l0.record(stream)
-            for _ in range(a.walk_reps):
-                tree.lists_build(reuse=True)
-            l1.record(stream)
-            torch.cuda.synchronize()
-            l2.record(stream)
-            for _ in range(a.walk_reps):
-                tree.lists_forces(acc)
-            l3.record(stream)
-            torch.cuda.synchronize()
-            nbytes = int(buf[:256 * 256].cpu().numpy().view(np.uint64)[::32].sum()) * 64 * 16
-            lists = {"build_ms": l0.elapsed_time(l1) / a.walk_reps, "eval_ms": l2.elapsed_time(l3) / a.walk_reps,
-                     "list_entry_bytes": nbytes, "bitwise_equal_to_walk": bool(torch.equal(acc, tree.forces()))}
-            del buf
+        l3.record(stream)
+        torch.cuda.synchronize()
+        nbytes = int(buf[:256 * 256].cpu().numpy().view(np.uint64)[::32].sum()) * 64 * 16
+        lists = {"build_ms": l0.elapsed_time(l1) / a.walk_reps, "eval_ms": l2.elapsed_time(l3) / a.walk_reps,
+                 "list_entry_bytes": nbytes, "bitwise_equal_to_walk": bool(torch.equal(acc, tree.forces()))}
+        del buf
         st = tree.forces_stats()
         torch.cuda.synchronize()
         tot = st["totals"]
@@ -420,6 +418,8 @@ def main():
                      "build_upward_ms": rr["ms_build_upward"],
                      "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s",
                                   "frac": ach / pk}}
+        if rr.get("lists"):
+            out[prec]["two_phase_lists"] = rr["lists"]
 
     if a.serve_requests > 0:
         out["serving"] = serve(a, bh, ctx, torch)

@@ -185,15 +185,15 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, 
  * interaction list of cubes and bodies is formed, flattened, then evaluated).
  * Phase one, bh_lists_build, walks the tree with bh_forces's decisions and
  * writes the lists into a caller buffer; phase two, bh_lists_forces, evaluates
- * them and gives bh_forces's acc and pot bit for bit.  FP32 trees with the
- * monopole expansion and the per-body test (any opening radius) only;
- * otherwise BH_E_INVAL.
+ * them and gives bh_forces's acc and pot bit for bit.  Trees with the
+ * monopole expansion and the per-body test (any opening radius, either
+ * precision) only; otherwise BH_E_INVAL.
  *
  * Lists are kept per walk group: group g holds the bodies of sorted ranks
  * [64 g, min(64 g + 64, n)); bit k of a mask is the group's k-th body.
  * Entry (a, b, mask), in walk order:
  *   a == 0xffffffff        start of a stack entry with b children (it times
- *                          the compensated-sum folds);
+ *                          the compensated-sum folds; FP32 lists only);
  *   b & 0x80000000         an opened leaf: particles of sorted ranks
  *                          [a, a + (b & 0x7fffffff)), paired with the bodies
  *                          in mask (not with themselves);

@@ -1069,7 +1069,7 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
 // order: the start of each stack entry (its child count, which times the
 // Kahan folds), each opened leaf (particle range, mask) and each accepted cube
 // (walk slot, node id, mask).  Phase two replays the lists with k_walk32's
-// arithmetic, so both give the same bits.  Monopole FP32 walks only.
+// arithmetic, so both give the same bits.  Monopole walks, FP32 and FP64.
 
 constexpr uint32_t kListEntry = 0xffffffffu;   // a == kListEntry: stack entry, b = children
 constexpr uint32_t kListLeaf = 0x80000000u;    // b & kListLeaf: leaf, a = first rank, b = particles
@@ -1398,9 +1398,239 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
     }
 }
 
+// FP64 lists: k_walk64's decisions and order (no compensated sums, so no stack
+// entry records); phase two replays them with k_walk64's arithmetic.
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_lists64(ForestDev f, ListDev ld) {
+    __shared__ WaveLds64<false> lds_all[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    WaveLds64<false> &L = lds_all[wave];
+    const uint32_t gi = blockIdx.x * W + wave;
+    if (gi >= f.ngroups) return;
+    if (uni(*f.err) & kErrTree) return;
+    const GroupDesc gd = f.groups[gi];
+    const uint32_t sid = uni(gd.seg);
+    const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 0 || sd.group || sd.quad) return;   // refused by the host
+    const uint32_t gstart = uni(gd.start);
+    const bool live = (uint32_t)lane < gd.count;
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
+    const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
+    const double theta2 = __dmul_rn(sd.theta, sd.theta);
+
+    uint32_t ne = 0, total = 0, prev = kListNone;
+    unsigned long long res = 0;
+    uint32_t nres = 0;
+    uint4 mine = make_uint4(0, 0, 0, 0);
+    auto flush_chunk = [&]() {
+        const uint32_t part = gi % kListParts;
+        if (nres == 0) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(ld.ctr + (size_t)part * 32, (unsigned long long)kListReserve);
+            res = __shfl(base, 0, 64);
+            nres = kListReserve;
+        }
+        const unsigned long long id = res * kListParts + part;
+        ++res;
+        --nres;
+        if (id < ld.nchunks) {
+            if ((uint32_t)lane < ne) ld.ent[id * 64 + lane] = mine;
+            if (lane == 0) {
+                if (prev == kListNone) ld.head[gi] = (uint32_t)id;
+                else ld.next[prev] = (uint32_t)id;
+                ld.next[id] = kListNone;
+            }
+        }
+        prev = id < ld.nchunks ? (uint32_t)id : kListNone;
+        total += ne;
+        ne = 0;
+    };
+    auto emit = [&](uint32_t a, uint32_t b, uint64_t m) {
+        if ((uint32_t)lane == ne) mine = make_uint4(a, b, (uint32_t)m, (uint32_t)(m >> 32));
+        if (++ne == 64) flush_chunk();
+    };
+
+    int sp = 0;
+    const uint64_t m0 = ballot(live);
+    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
+    wave_sync();
+    sp = 1;
+    while (sp > 0) {
+        --sp;
+        const uint4 e = L.stk[sp];
+        const uint32_t link = uni(e.x), nch = uni(e.y);
+        const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+        wave_sync();
+        if ((uint32_t)lane < nch) {
+            const WRec64 &w = f.w64[link + lane];
+            L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
+            L.sS[lane] = w.S;
+            L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
+        }
+        wave_sync();
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
+            const double4 qa = L.sa[c];
+            const double S = L.sS[c];
+            const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
+            const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            const uint64_t accm = ballot(S < __dmul_rn(theta2, D2)) & emask;
+            const uint64_t open = emask & ~accm;
+            if (open) {
+                const uint4 qb = L.sb[c];
+                const uint32_t qlink = uni(qb.x), qcnt = uni(qb.y);
+                if (qcnt & kLeafBit) {
+                    emit(qlink, kListLeaf | (qcnt & ~kLeafBit), open);
+                } else if (sp < kStackMax) {
+                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
+                    wave_sync();
+                    ++sp;
+                } else if (lane == 0) {
+                    atomicOr(f.err, kErrStack);
+                }
+            }
+            if (accm) emit(link + c, uni(L.sb[c].z), accm);
+        }
+    }
+    if (ne) flush_chunk();
+    if (lane == 0) ld.count[gi] = total;
+}
+
+template <bool POT>
+__global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, WalkOut out) {
+    __shared__ WaveLds64<false> lds_all[4];
+    __shared__ double4 mst_all[4][64];   // accepted cubes of the current chunk: centre, mass
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    WaveLds64<false> &L = lds_all[wave];
+    double4 *mst = mst_all[wave];
+    const uint32_t gi = blockIdx.x * 4 + wave;
+    if (gi >= f.ngroups) return;
+    if (uni(*f.err) & (kErrTree | kErrStack)) return;
+    const GroupDesc gd = f.groups[gi];
+    const uint32_t sid = uni(gd.seg);
+    const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 0 || sd.group || sd.quad) return;
+    const uint32_t gstart = uni(gd.start);
+    const bool live = (uint32_t)lane < gd.count;
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
+    const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
+    const double eps2 = __dmul_rn(sd.eps, sd.eps);
+    const bool soft = eps2 > 0.0;
+
+    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
+    uint32_t qn = 0;
+    auto pair = [&](double px, double py, double pz, double pm) {
+        const double dx = px - tx, dy = py - ty, dz = pz - tz;
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+        if (soft || r2 > 0.0) {
+            const double ri = rsqrt64(r2);
+            const double mr = pm * ri;
+            const double w3 = mr * ri * ri;
+            ax = fma(w3, dx, ax);
+            ay = fma(w3, dy, ay);
+            az = fma(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    };
+    auto flush_leaves = [&]() {
+        if (qn == 0) return;
+        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+            wave_sync();
+            if ((uint32_t)lane < nb) {
+                const size_t j = L.irank[k0 + lane];
+                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+            }
+            wave_sync();
+            for (uint32_t k = 0; k < nb; ++k) {
+                const uint32_t jq = uni(L.irank[k0 + k]);
+                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                if (in_mask(m)) {
+                    const double4 p = L.pst[k];
+                    pair(p.x, p.y, p.z, p.w);
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    const uint32_t n = uni(ld.count[gi]);
+    uint32_t chunk = uni(ld.head[gi]);
+    for (uint32_t k0 = 0; k0 < n; k0 += 64) {
+        const uint32_t nb = n - k0 < 64u ? n - k0 : 64u;
+        const uint4 mine = (uint32_t)lane < nb ? ld.ent[(size_t)chunk * 64 + lane] : make_uint4(0, 0, 0, 0);
+        wave_sync();
+        if ((uint32_t)lane < nb && mine.x != kListEntry && !(mine.y & kListLeaf)) {
+            const WRec64 &w = f.w64[mine.x];
+            mst[lane] = make_double4(w.x, w.y, w.z, w.m);
+        }
+        wave_sync();
+        for (uint32_t k = 0; k < nb; ++k) {
+            const uint32_t a = (uint32_t)__builtin_amdgcn_readlane(mine.x, k);
+            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(mine.y, k);
+            const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.w, k) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.z, k);
+            if (a == kListEntry) continue;
+            if (b & kListLeaf) {
+                const uint32_t np = b & ~kListLeaf;
+                if (np <= 64u) {
+                    if (qn + np > 64u) flush_leaves();
+                    if ((uint32_t)lane < np) {
+                        L.irank[qn + lane] = a + lane;
+                        L.imask[qn + lane] = m;
+                    }
+                    qn += np;
+                } else {
+                    flush_leaves();
+                    for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                        const uint32_t nq = np - b0 < 64u ? np - b0 : 64u;
+                        if ((uint32_t)lane < nq) {
+                            L.irank[lane] = a + b0 + lane;
+                            L.imask[lane] = m;
+                        }
+                        qn = nq;
+                        flush_leaves();
+                    }
+                }
+            } else if (in_mask(m)) {
+                const double4 qa = mst[k];
+                const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
+                const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                const double E2 = D2 + eps2;
+                const double ri = rsqrt64(E2);
+                const double mr = qa.w * ri;
+                const double ri2 = ri * ri;
+                const double w3 = mr * ri2;
+                ax = fma(w3, dx, ax);
+                ay = fma(w3, dy, ay);
+                az = fma(w3, dz, az);
+                if (POT) ap -= mr;
+            }
+        }
+        chunk = uni(ld.next[chunk]);
+    }
+    flush_leaves();
+    if (live) {
+        const uint32_t i = f.idx[r];
+        const size_t li = i - sd.start;
+        const double G = sd.G;
+        double *accb = seg_base(out.acc, sd.acc, sd, 3);
+        accb[3 * li] = G * ax;
+        accb[3 * li + 1] = G * ay;
+        accb[3 * li + 2] = G * az;
+        if (POT) {
+            double *potb = seg_base(out.pot, sd.pot, sd, 1);
+            if (potb) potb[li] = G * ap;
+        }
+    }
+}
+
 hipError_t launch_lists_build(const ForestDev &f, const ListDev &ld, hipStream_t s) {
     if (f.ngroups == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_lists32<4>), dim3((f.ngroups + 3) / 4), dim3(256), 0, s, f, ld);
+    if (f.has32) hipLaunchKernelGGL((k_lists32<4>), dim3((f.ngroups + 3) / 4), dim3(256), 0, s, f, ld);
+    if (f.has64) hipLaunchKernelGGL((k_lists64<4>), dim3((f.ngroups + 3) / 4), dim3(256), 0, s, f, ld);
     return hipGetLastError();
 }
 
@@ -1414,9 +1644,11 @@ hipError_t launch_lists_eval(const ForestDev &f, const ListDev &ld, bool want_po
     if (want_pot) {
         if (soft) hipLaunchKernelGGL((k_lists_eval32<true, true, 4>), g, b, 0, s, f, ld, o);
         if (unsoft) hipLaunchKernelGGL((k_lists_eval32<true, false, 4>), g, b, 0, s, f, ld, o);
+        if (f.has64) hipLaunchKernelGGL((k_lists_eval64<true>), g, b, 0, s, f, ld, o);
     } else {
         if (soft) hipLaunchKernelGGL((k_lists_eval32<false, true, 4>), g, b, 0, s, f, ld, o);
         if (unsoft) hipLaunchKernelGGL((k_lists_eval32<false, false, 4>), g, b, 0, s, f, ld, o);
+        if (f.has64) hipLaunchKernelGGL((k_lists_eval64<false>), g, b, 0, s, f, ld, o);
     }
     return hipGetLastError();
 }

@@ -1,5 +1,5 @@
-"""Two-phase force stage (bh_lists_build, bh_lists_forces): the evaluated lists give the
-single-pass walk's forces bit for bit, and the lists themselves, decoded per body, are the
+"""Two-phase force stage (bh_lists_build, bh_lists_forces), both precisions: the evaluated
+lists give the single-pass walk's forces bit for bit, and the lists themselves, decoded per body, are the
 oracle's interaction sets (counts and checksums); buffer sizing and refusals."""
 import ctypes as C
 
@@ -50,12 +50,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("kind,n,seed,theta,eps,cap,open_", CASES)
-def test_lists_give_the_walks_bits(ctx, kind, n, seed, theta, eps, cap, open_):
-    print(f"[lists] {kind} n={n} theta={theta} eps={eps} leaf_cap={cap} {open_}", flush=True)
+def test_lists_give_the_walks_bits(ctx, kind, n, seed, theta, eps, cap, open_, prec):
+    print(f"[lists] {kind} n={n} theta={theta} eps={eps} leaf_cap={cap} {open_} {prec}", flush=True)
     s = make(kind, n, seed)
     t = bh.Tree(ctx, dev(s.pos), dev(s.mass),
-                bh.params(theta, eps, leaf_cap=cap, precision="fp32", open=open_)).upward()
+                bh.params(theta, eps, leaf_cap=cap, precision=prec, open=open_)).upward()
     a, p = t.forces(pot=True)
     t.lists_build()
     b, q = t.lists_forces(pot=True)
@@ -115,11 +116,13 @@ def decode(buf, n):
     return out
 
 
-@pytest.mark.parametrize("kind,n,seed,theta,cap", [("plummer", 4096, 2, 0.6, 4), ("duplicates", 3000, 8, 0.8, 1)])
-def test_lists_are_the_oracle_sets(ctx, kind, n, seed, theta, cap):
+@pytest.mark.parametrize("kind,n,seed,theta,cap,prec", [("plummer", 4096, 2, 0.6, 4, "fp32"),
+                                                        ("duplicates", 3000, 8, 0.8, 1, "fp32"),
+                                                        ("plummer", 4096, 2, 0.6, 4, "fp64")])
+def test_lists_are_the_oracle_sets(ctx, kind, n, seed, theta, cap, prec):
     s = make(kind, n, seed)
     ref = oracle.Tree(s.pos, s.mass, cap).walk(theta, 0.01)
-    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(theta, 0.01, leaf_cap=cap, precision="fp32")).upward()
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(theta, 0.01, leaf_cap=cap, precision=prec)).upward()
     ex = t.export(with_mass=False)
     perm = ex["perm"].cpu().numpy().astype(np.int64)
     nn = ex["n_nodes"]
@@ -174,7 +177,7 @@ def test_buffer_sizing_and_validity(ctx):
 
 def test_unsupported_trees_refused(ctx):
     s = icgen.plummer(2000, 4)
-    for p in (bh.params(0.5, 0.01, precision="fp64"), bh.params(0.5, 0.01, precision="fp32", quad=True),
+    for p in (bh.params(0.5, 0.01, precision="fp32", quad=True), bh.params(0.5, 0.01, precision="fp64", quad=True),
               bh.params(0.5, 0.01, precision="fp32", group=True)):
         t = bh.Tree(ctx, dev(s.pos), dev(s.mass), p).upward()
         with pytest.raises(bh.BHError):
