@@ -186,8 +186,8 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, 
  * Phase one, bh_lists_build, walks the tree with bh_forces's decisions and
  * writes the lists into a caller buffer; phase two, bh_lists_forces, evaluates
  * them and gives bh_forces's acc and pot bit for bit.  Trees with the
- * monopole expansion and the per-body test (any opening radius, either
- * precision) only; otherwise BH_E_INVAL.
+ * per-body test (any opening radius, either precision, with or without the
+ * quadrupole) only; BH_GROUP_CRITERION trees give BH_E_INVAL.
  *
  * Lists are kept per walk group: group g holds the bodies of sorted ranks
  * [64 g, min(64 g + 64, n)); bit k of a mask is the group's k-th body.

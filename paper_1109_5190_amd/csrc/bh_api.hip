@@ -425,8 +425,7 @@ ListDev list_dev(void *buf, size_t ngroups, size_t nchunks) {
 
 bh_status lists_supported(const bh_tree *t) {
     for (const SegDesc &d : t->F.seg)
-        if (d.quad || d.group)
-            return bh_fail(BH_E_INVAL, "interaction lists: trees with the monopole and the per-body test only");
+        if (d.group) return bh_fail(BH_E_INVAL, "interaction lists: trees with the per-body test only");
     return BH_OK;
 }
 

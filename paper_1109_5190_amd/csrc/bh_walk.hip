@@ -1069,7 +1069,8 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
 // order: the start of each stack entry (its child count, which times the
 // Kahan folds), each opened leaf (particle range, mask) and each accepted cube
 // (walk slot, node id, mask).  Phase two replays the lists with k_walk32's
-// arithmetic, so both give the same bits.  Monopole walks, FP32 and FP64.
+// arithmetic, so both give the same bits.  Per-body walks of either precision
+// and expansion order.
 
 constexpr uint32_t kListEntry = 0xffffffffu;   // a == kListEntry: stack entry, b = children
 constexpr uint32_t kListLeaf = 0x80000000u;    // b & kListLeaf: leaf, a = first rank, b = particles
@@ -1086,7 +1087,7 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 1 || sd.group || sd.quad) return;   // refused by the host
+    if (sd.precision != 1 || sd.group) return;   // refused by the host
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
@@ -1210,7 +1211,7 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     if (lane == 0) ld.count[gi] = total;
 }
 
-template <bool POT, bool SOFT, int W>
+template <bool POT, bool SOFT, int W, bool QUAD>
 __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld, WalkOut out) {
     __shared__ WaveLds32 lds_all[W];
     __shared__ float4 mst_all[W][64];   // accepted cubes of the current chunk: centre rel g, mass
@@ -1223,7 +1224,7 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 1 || sd.group || sd.quad || unsoftened(sd.eps) == SOFT) return;
+    if (sd.precision != 1 || sd.group || (sd.quad != 0) != QUAD || unsoftened(sd.eps) == SOFT) return;
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
@@ -1373,6 +1374,45 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
                 const float mr = qa.w * ri;
                 const float ri2 = ri * ri;
                 const float w3 = mr * ri2;
+                if (QUAD) {
+                    // the walk's quadrupole term, from the moments of walk slot a
+                    const float4 s0 = f.q32[2 * (size_t)a], s1 = f.q32[2 * (size_t)a + 1];
+                    const float sdx = fmaf(s0.x, dx, fmaf(s0.w, dy, s1.x * dz));
+                    const float sdy = fmaf(s0.w, dx, fmaf(s0.y, dy, s1.y * dz));
+                    const float sdz = fmaf(s1.x, dx, fmaf(s1.y, dy, s0.z * dz));
+                    const float A = fmaf(3.0f, fmaf(dx, sdx, fmaf(dy, sdy, dz * sdz)), -E2 * s1.z);
+                    const float ri5 = ri2 * ri2 * ri;
+                    float qx = -ri5 * fmaf(3.0f, sdx, -s1.z * dx) + 2.5f * A * ri5 * ri2 * dx;
+                    float qy = -ri5 * fmaf(3.0f, sdy, -s1.z * dy) + 2.5f * A * ri5 * ri2 * dy;
+                    float qz = -ri5 * fmaf(3.0f, sdz, -s1.z * dz) + 2.5f * A * ri5 * ri2 * dz;
+                    float qp = -0.5f * A * ri5;
+                    const uint64_t hard = ballot(s1.z > qa.w * E2) & m;
+                    if (hard) {
+                        if (in_mask(hard)) {
+                            const WRec32 &wc = f.w32[a];
+                            const double cm[3] = {wc.cx, wc.cy, wc.cz};
+                            const double *xp = f.spos + 3 * (size_t)r;
+                            const double *S = f.uQ + 6 * (size_t)a;
+                            const double ex_ = cm[0] - xp[0], ey = cm[1] - xp[1], ez = cm[2] - xp[2];
+                            const double e2 = ((ex_ * ex_ + ey * ey) + ez * ez) + (double)sd.eps * sd.eps;
+                            const double tr = (S[0] + S[1]) + S[2];
+                            const double sx = fma(S[0], ex_, fma(S[3], ey, S[4] * ez));
+                            const double sy = fma(S[3], ex_, fma(S[1], ey, S[5] * ez));
+                            const double sz = fma(S[4], ex_, fma(S[5], ey, S[2] * ez));
+                            const double A64 = fma(3.0, fma(ex_, sx, fma(ey, sy, ez * sz)), -e2 * tr);
+                            const double rinv = 1.0 / sqrt(e2);
+                            const double r5 = rinv * rinv * rinv * rinv * rinv, r7 = r5 * rinv * rinv;
+                            qx = (float)(2.5 * A64 * r7 * ex_ - r5 * fma(3.0, sx, -tr * ex_));
+                            qy = (float)(2.5 * A64 * r7 * ey - r5 * fma(3.0, sy, -tr * ey));
+                            qz = (float)(2.5 * A64 * r7 * ez - r5 * fma(3.0, sz, -tr * ez));
+                            qp = (float)(-0.5 * A64 * r5);
+                        }
+                    }
+                    ax += qx;
+                    ay += qy;
+                    az += qz;
+                    if (POT) ap += qp;
+                }
                 ax = fmaf(w3, dx, ax);
                 ay = fmaf(w3, dy, ay);
                 az = fmaf(w3, dz, az);
@@ -1411,7 +1451,7 @@ __global__ void __launch_bounds__(64 * W) k_lists64(ForestDev f, ListDev ld) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 0 || sd.group || sd.quad) return;   // refused by the host
+    if (sd.precision != 0 || sd.group) return;   // refused by the host
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
@@ -1497,7 +1537,7 @@ __global__ void __launch_bounds__(64 * W) k_lists64(ForestDev f, ListDev ld) {
     if (lane == 0) ld.count[gi] = total;
 }
 
-template <bool POT>
+template <bool POT, bool QUAD>
 __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, WalkOut out) {
     __shared__ WaveLds64<false> lds_all[4];
     __shared__ double4 mst_all[4][64];   // accepted cubes of the current chunk: centre, mass
@@ -1510,7 +1550,7 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 0 || sd.group || sd.quad) return;
+    if (sd.precision != 0 || sd.group || (sd.quad != 0) != QUAD) return;
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
@@ -1602,7 +1642,22 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
                 const double ri = rsqrt64(E2);
                 const double mr = qa.w * ri;
                 const double ri2 = ri * ri;
-                const double w3 = mr * ri2;
+                double w3 = mr * ri2;
+                if (QUAD) {
+                    // the walk's quadrupole term, from the moments of walk slot a
+                    const double *q = f.q64 + 6 * (size_t)a;
+                    const double sdx = fma(q[0], dx, fma(q[3], dy, q[4] * dz));
+                    const double sdy = fma(q[3], dx, fma(q[1], dy, q[5] * dz));
+                    const double sdz = fma(q[4], dx, fma(q[5], dy, q[2] * dz));
+                    const double tr = (q[0] + q[1]) + q[2];
+                    const double A = fma(3.0, fma(dx, sdx, fma(dy, sdy, dz * sdz)), -E2 * tr);
+                    const double ri5 = ri2 * ri2 * ri;
+                    w3 = fma(2.5 * A, ri5 * ri2, w3);
+                    ax = fma(-ri5, fma(3.0, sdx, -tr * dx), ax);
+                    ay = fma(-ri5, fma(3.0, sdy, -tr * dy), ay);
+                    az = fma(-ri5, fma(3.0, sdz, -tr * dz), az);
+                    if (POT) ap -= 0.5 * A * ri5;
+                }
                 ax = fma(w3, dx, ax);
                 ay = fma(w3, dy, ay);
                 az = fma(w3, dz, az);
@@ -1634,22 +1689,24 @@ hipError_t launch_lists_build(const ForestDev &f, const ListDev &ld, hipStream_t
     return hipGetLastError();
 }
 
+template <bool POT>
+static void launch_lists_eval_p(const ForestDev &f, const ListDev &ld, const WalkOut &o, hipStream_t s) {
+    const dim3 g((f.ngroups + 3) / 4), b(256);
+    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_lists_eval32<POT, true, 4, false>), g, b, 0, s, f, ld, o);
+    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_lists_eval32<POT, true, 4, true>), g, b, 0, s, f, ld, o);
+    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_lists_eval32<POT, false, 4, false>), g, b, 0, s, f, ld, o);
+    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_lists_eval32<POT, false, 4, true>), g, b, 0, s, f, ld, o);
+    if (f.has64 & (var_bit(false, false) | var_bit(false, true)))
+        hipLaunchKernelGGL((k_lists_eval64<POT, false>), g, b, 0, s, f, ld, o);
+    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_lists_eval64<POT, true>), g, b, 0, s, f, ld, o);
+}
+
 hipError_t launch_lists_eval(const ForestDev &f, const ListDev &ld, bool want_pot, double *acc, double *pot,
                              hipStream_t s) {
     if (f.ngroups == 0) return hipSuccess;
     WalkOut o{acc, pot, nullptr, nullptr, nullptr};
-    const dim3 g((f.ngroups + 3) / 4), b(256);
-    const bool soft = (f.has32 & (var_bit(false, false) | var_bit(true, false))) != 0;
-    const bool unsoft = (f.has32 & (var_bit(false, true) | var_bit(true, true))) != 0;
-    if (want_pot) {
-        if (soft) hipLaunchKernelGGL((k_lists_eval32<true, true, 4>), g, b, 0, s, f, ld, o);
-        if (unsoft) hipLaunchKernelGGL((k_lists_eval32<true, false, 4>), g, b, 0, s, f, ld, o);
-        if (f.has64) hipLaunchKernelGGL((k_lists_eval64<true>), g, b, 0, s, f, ld, o);
-    } else {
-        if (soft) hipLaunchKernelGGL((k_lists_eval32<false, true, 4>), g, b, 0, s, f, ld, o);
-        if (unsoft) hipLaunchKernelGGL((k_lists_eval32<false, false, 4>), g, b, 0, s, f, ld, o);
-        if (f.has64) hipLaunchKernelGGL((k_lists_eval64<false>), g, b, 0, s, f, ld, o);
-    }
+    if (want_pot) launch_lists_eval_p<true>(f, ld, o, s);
+    else launch_lists_eval_p<false>(f, ld, o, s);
     return hipGetLastError();
 }
 

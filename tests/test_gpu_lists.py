@@ -64,6 +64,20 @@ def test_lists_give_the_walks_bits(ctx, kind, n, seed, theta, eps, cap, open_, p
     assert torch.equal(t.lists_forces(), a)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("kind,n,seed,theta,eps", [("plummer", 6000, 9, 0.7, 0.01), ("plummer", 20000, 4, 1.0, 0.0),
+                                                   ("cube", 8000, 5, 0.6, 0.005)])
+def test_lists_with_quadrupole(ctx, kind, n, seed, theta, eps, prec):
+    """Quadrupole trees: the replay adds the walk's quadrupole term (and, in FP32, its FP64 lanes
+    for bodies close to a cube) in the same order, so the bits are the walk's."""
+    s = make(kind, n, seed)
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(theta, eps, precision=prec, quad=True)).upward()
+    a, p = t.forces(pot=True)
+    t.lists_build()
+    b, q = t.lists_forces(pot=True)
+    assert torch.equal(a, b) and torch.equal(p, q)
+
+
 def up256(v):
     return (v + 255) & ~255
 
@@ -177,8 +191,7 @@ def test_buffer_sizing_and_validity(ctx):
 
 def test_unsupported_trees_refused(ctx):
     s = icgen.plummer(2000, 4)
-    for p in (bh.params(0.5, 0.01, precision="fp32", quad=True), bh.params(0.5, 0.01, precision="fp64", quad=True),
-              bh.params(0.5, 0.01, precision="fp32", group=True)):
+    for p in (bh.params(0.5, 0.01, precision="fp32", group=True), bh.params(0.5, 0.01, precision="fp64", group=True)):
         t = bh.Tree(ctx, dev(s.pos), dev(s.mass), p).upward()
         with pytest.raises(bh.BHError):
             t.lists_build()
