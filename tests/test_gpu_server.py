@@ -117,3 +117,39 @@ def test_cancel(ctx):
     c = sv.submit(1000, 2, 0, 3, bh.params(), 1e-3)
     assert wait(sv, c)["state"] == "done"
     sv.close()
+
+
+VARIANT_REQS = [  # (n, steps, kind, seed, theta, precision, option)
+    (4000, 3, 0, 201, 0.6, "fp32", dict(quad=True)),
+    (6000, 2, 1, 202, 0.8, "fp64", dict(open="bmax")),
+    (3000, 4, 0, 203, 0.7, "fp32", dict(open="offset")),
+    (5000, 2, 0, 204, 0.5, "fp64", dict(group=True)),
+    (2500, 3, 1, 205, 0.6, "fp64", dict(quad=True, open="offset")),
+]
+
+
+def test_options_alone_equal_mix_and_plain_simulation(ctx):
+    """Requests with the quadrupole, the alternative radii and the group criterion, mixed with
+    each other in one forest iteration, give the bits they give alone and under bh_sim."""
+    def sub(sv, req):
+        n, steps, kind, seed, theta, prec, opt = req
+        return sv.submit(n, steps, kind, seed, bh.params(theta, 0.01, precision=prec, **opt), 1e-3)
+
+    sv = bh.Server(ctx, 2 * GiB, max_slots=16, max_resident=1 << 20)
+    alone = []
+    for req in VARIANT_REQS:
+        rid = sub(sv, req)
+        assert wait(sv, rid)["state"] == "done"
+        alone.append(sv.fetch(rid, req[0]))
+    ids = [sub(sv, req) for req in VARIANT_REQS]
+    for k, (rid, req) in enumerate(zip(ids, VARIANT_REQS)):
+        assert wait(sv, rid)["state"] == "done"
+        pm, vm = sv.fetch(rid, req[0])
+        assert torch.equal(alone[k][0], pm) and torch.equal(alone[k][1], vm), k
+    sv.close()
+    for k, (n, steps, kind, seed, theta, prec, opt) in enumerate(VARIANT_REQS):
+        pos, vel, mass = bh.ic_generate(ctx, kind, n, seed)
+        sim = bh.Sim(ctx, pos, vel, mass, bh.params(theta, 0.01, precision=prec, **opt))
+        sim.step(steps, 1e-3)
+        ctx.sync()
+        assert torch.equal(pos, alone[k][0]) and torch.equal(vel, alone[k][1]), k
