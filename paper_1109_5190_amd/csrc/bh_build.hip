@@ -476,40 +476,46 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, cons
 
 // ================================================================ permute ===
 
-__global__ void k_permute(ForestDev f) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= f.ntot) return;
-    const SegDesc &sd = f.seg[f.segid[r]];
-    const size_t li = f.idx[r] - sd.start;
-    if (li >= sd.n) {   // cannot happen after a correct sort
-        atomicOr(f.err, kErrTree);
-        return;
+// One pass over the sorted rows r in [0, ntot]: the state in key order (gathered
+// from the packed records), the common-prefix level of neighbouring keys (-1 at
+// the first row of each simulation and at the end), the cleared node-start masks,
+// and the node tables cleared for the fill pass (two ids per row: the node
+// capacity is twice the rows).
+__global__ void k_permute_lcp(ForestDev f) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > f.ntot) return;
+    for (uint32_t g = r; g < f.mcap; g += f.ntot + 1) {
+        f.nchild[g] = 0;
+        f.nparent[g] = kNone;
+        f.ncrank[g] = kNone;
     }
-    const double4 p = f.pk[sd.start + li];
-    f.spos[3 * (size_t)r] = p.x;
-    f.spos[3 * (size_t)r + 1] = p.y;
-    f.spos[3 * (size_t)r + 2] = p.z;
-    f.smass[r] = p.w;
+    int8_t v = -1;
+    if (r < f.ntot) {
+        f.mask[r] = 0;
+        const uint32_t s = f.segid[r];
+        const SegDesc &sd = f.seg[s];
+        if (r != sd.start) {
+            const uint64_t x = f.keys[r - 1] ^ f.keys[r];
+            v = x == 0 ? (int8_t)kMaxLevel : (int8_t)((__clzll((long long)x) - 1) / 3);
+        }
+        const size_t li = f.idx[r] - sd.start;
+        if (li >= sd.n) {   // cannot happen after a correct sort
+            atomicOr(f.err, kErrTree);
+        } else {
+            const double4 p = f.pk[sd.start + li];
+            f.spos[3 * (size_t)r] = p.x;
+            f.spos[3 * (size_t)r + 1] = p.y;
+            f.spos[3 * (size_t)r + 2] = p.z;
+            f.smass[r] = p.w;
+        }
+    }
+    f.lcp[r] = v;
 }
 
 // ==================================================================== lcp ===
 // lcp[p], p in [0, ntot]: octant digits shared by keys p-1 and p (21 if equal),
 // -1 at the first row of a simulation and at ntot.  Also clears mask.
 
-__global__ void k_lcp(ForestDev f) {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > f.ntot) return;
-    int8_t v = -1;
-    if (p < f.ntot) {
-        f.mask[p] = 0;
-        uint32_t s = f.segid[p];
-        if (p != f.seg[s].start) {
-            uint64_t x = f.keys[p - 1] ^ f.keys[p];
-            v = x == 0 ? (int8_t)kMaxLevel : (int8_t)((__clzll((long long)x) - 1) / 3);
-        }
-    }
-    f.lcp[p] = v;
-}
 
 // ============================================================ node marking ===
 
@@ -587,16 +593,6 @@ __global__ void __launch_bounds__(256) k_mark(ForestDev f) {
 
 constexpr uint32_t kInner = 0xFFFFFFFFu;   // nchild of an internal node until its children are linked
 
-// Node tables before the fill pass: no children, no parent, no rank (every id
-// below the node count is then written by k_fill or k_link; the rest stays
-// clear for the child-count scan over the capacity).
-__global__ void k_clear_nodes(ForestDev f) {
-    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < f.mcap; g += (size_t)gridDim.x * blockDim.x) {
-        f.nchild[g] = 0;
-        f.nparent[g] = kNone;
-        f.ncrank[g] = kNone;
-    }
-}
 
 // Fill pass: node records (level, first rows, count) at their preorder ids.
 __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
@@ -740,16 +736,10 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
     const unsigned nb = (f.ntot + 255) / 256;
-    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_lcp, dim3((f.ntot + 1 + 255) / 256), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_permute_lcp, dim3((f.ntot + 1 + 255) / 256), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_mark, dim3(nb), dim3(256), 0, s, f);
     hipError_t e = scan_exclusive(f.mask, f.ntot, f.base, f.scan_tmp, 1, s);
     if (e != hipSuccess) return e;
-    {
-        unsigned fb = (f.mcap + 255) / 256;
-        if (fb > 4096) fb = 4096;
-        hipLaunchKernelGGL(k_clear_nodes, dim3(fb), dim3(256), 0, s, f);
-    }
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, f);
     const unsigned mb = (f.mcap + 255) / 256;
     hipLaunchKernelGGL(k_link, dim3(mb), dim3(256), 0, s, f);
