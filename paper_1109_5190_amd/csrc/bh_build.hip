@@ -328,23 +328,24 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dig, uint64_t valid) {
 
 
 
-__global__ void __launch_bounds__(kSortThreads) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
-    __shared__ uint32_t hist[kSortWaves][256];
+template <int T>
+__global__ void __launch_bounds__(T) k_sort_hist(ForestDev f, const uint64_t *keys, int shift) {
+    __shared__ uint32_t hist[(T / 64)][256];
     const TileDesc td = f.tiles[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = lane; d < 256; d += 64) hist[wave][d] = 0;
     __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
-    uint32_t dg[kSortItems];
-    bool ok[kSortItems];
+    uint32_t dg[(kTile / T)];
+    bool ok[(kTile / T)];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < (kTile / T); ++j) {
+        const uint32_t e = (uint32_t)wave * 64 * (kTile / T) + (uint32_t)j * 64 + lane;
         ok[j] = e < td.count;
         dg[j] = ok[j] ? (uint32_t)(keys[(size_t)td.start + e] >> shift) & 255u : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < (kTile / T); ++j) {
         const uint64_t peers = match_digit(dg[j], __ballot(ok[j]));
         if (ok[j] && (peers & lt) == 0) hist[wave][dg[j]] += (uint32_t)__popcll(peers);
     }
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(ForestDev f, const u
         const uint32_t d = threadIdx.x;
         uint32_t t = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) t += hist[w][d];
+        for (int w = 0; w < (T / 64); ++w) t += hist[w][d];
         f.cnt[256u * blockIdx.x + d] = t;
     }
 }
@@ -390,33 +391,34 @@ __global__ void __launch_bounds__(256) k_sort_colscan(ForestDev f) {
     }
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
+template <int T>
+__global__ void __launch_bounds__(T) k_sort_scatter(ForestDev f, const uint64_t *kin, const uint32_t *iin,
                                                                uint64_t *kout, uint32_t *iout, int shift) {
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sidx[kTile];
-    __shared__ uint32_t whist[kSortWaves][256];
+    __shared__ uint32_t whist[(T / 64)][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t wtot[kSortWaves];
+    __shared__ uint32_t wtot[(T / 64)];
     const TileDesc td = f.tiles[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
     for (int d = lane; d < 256; d += 64) whist[wave][d] = 0;
     __syncthreads();
 
-    uint64_t key[kSortItems];
-    uint32_t idv[kSortItems];
-    uint32_t rank[kSortItems];
+    uint64_t key[(kTile / T)];
+    uint32_t idv[(kTile / T)];
+    uint32_t rank[(kTile / T)];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < (kTile / T); ++j) {
+        uint32_t e = (uint32_t)wave * 64 * (kTile / T) + (uint32_t)j * 64 + lane;
         bool valid = e < td.count;
         key[j] = valid ? kin[(size_t)td.start + e] : 0ull;
         idv[j] = valid ? iin[(size_t)td.start + e] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < (kTile / T); ++j) {
+        uint32_t e = (uint32_t)wave * 64 * (kTile / T) + (uint32_t)j * 64 + lane;
         bool valid = e < td.count;
         uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
         uint64_t peers = match_digit(dig, __ballot(valid));
@@ -430,10 +432,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, cons
     {
         const uint32_t d = threadIdx.x;
         uint32_t tot = 0;
-        uint32_t c[kSortWaves];
+        uint32_t c[(T / 64)];
         if (d < 256) {
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
+            for (int w = 0; w < (T / 64); ++w) {
                 c[w] = whist[w][d];
                 tot += c[w];
             }
@@ -446,7 +448,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, cons
             lstart[d] = inc - tot;
             uint32_t run = 0;
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
+            for (int w = 0; w < (T / 64); ++w) {
                 whist[w][d] = run;
                 run += c[w];
             }
@@ -455,8 +457,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, cons
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        uint32_t e = (uint32_t)wave * 64 * kSortItems + (uint32_t)j * 64 + lane;
+    for (int j = 0; j < (kTile / T); ++j) {
+        uint32_t e = (uint32_t)wave * 64 * (kTile / T) + (uint32_t)j * 64 + lane;
         if (e < td.count) {
             uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
             uint32_t p = lstart[dig] + whist[wave][dig] + rank[j];
@@ -465,7 +467,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(ForestDev f, cons
         }
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < td.count; q += kSortThreads) {
+    for (uint32_t q = threadIdx.x; q < td.count; q += T) {
         uint64_t k = skey[q];
         uint32_t dig = (uint32_t)(k >> shift) & 255u;
         uint32_t o = gbase[dig] + (q - lstart[dig]);
@@ -729,9 +731,15 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
     uint32_t *iin = f.idx, *iout = f.idx_alt;
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, kin, shift);
+        // the histogram takes 1024 threads per tile; the scatter (67 KB of LDS at 1024 threads)
+        // does too while there are at most two tiles per compute unit, and otherwise keeps
+        // more tiles resident with 256-thread blocks
+        hipLaunchKernelGGL(k_sort_hist<1024>, dim3(f.ntiles), dim3(1024), 0, s, f, kin, shift);
         hipLaunchKernelGGL(k_sort_colscan, dim3(256), dim3(256), 0, s, f);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(f.ntiles), dim3(kSortThreads), 0, s, f, kin, iin, kout, iout, shift);
+        if (f.ntiles <= 512)
+            hipLaunchKernelGGL(k_sort_scatter<1024>, dim3(f.ntiles), dim3(1024), 0, s, f, kin, iin, kout, iout, shift);
+        else
+            hipLaunchKernelGGL(k_sort_scatter<256>, dim3(f.ntiles), dim3(256), 0, s, f, kin, iin, kout, iout, shift);
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
