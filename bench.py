@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--walk-reps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=524288, help="oracle walk targets for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--shards", type=int, default=8, help="targets split for one GPU's share (0: skip)")
     ap.add_argument("--precisions", default="fp32,fp64")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
@@ -233,6 +234,41 @@ def batch(a, bh, torch):
                                       "sample": "256 targets on each of 8 instances stratified by N, initial positions"}}
 
 
+def one_gpu_share(a, tree, st, stream, torch, ms_walk):
+    """The walk of one GPU's share when the targets are split G ways (each GPU holding the whole
+    tree): ranges from the cost zones of the counts `st` of a previous walk, and from equal counts,
+    each walked alone on the whole GPU.  The ranges together reproduce the full walk's bits."""
+    G = a.shards
+    out = {"G": G}
+    b0, b1 = _events(torch)
+    b0.record(stream)
+    for _ in range(a.walk_reps):
+        bounds = tree.shard_bounds(G, st["n_mono"], st["n_p2p"])
+    b1.record(stream)
+    torch.cuda.synchronize()
+    out["bounds_ms"] = b0.elapsed_time(b1) / a.walk_reps
+    acc = torch.empty_like(st["acc"])
+    for name, bl in (("cost_zones", bounds.cpu().tolist()), ("equal_counts", tree.shard_bounds(G).cpu().tolist())):
+        ms = []
+        for j in range(G):
+            tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            for _ in range(a.walk_reps):
+                tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / a.walk_reps)
+        out[name] = {"ms": ms, "max_ms": max(ms), "sum_ms": sum(ms), "imbalance": max(ms) * G / sum(ms),
+                     "full_walk_over_G_vs_max": ms_walk / G / max(ms),
+                     "bitwise_equal_to_walk": bool(torch.equal(acc, st["acc"]))}
+    print(f"# one GPU's share of {G}: cost zones max {out['cost_zones']['max_ms']:.3f} ms "
+          f"(imbalance {out['cost_zones']['imbalance']:.3f}), equal counts max "
+          f"{out['equal_counts']['max_ms']:.3f} ms (imbalance {out['equal_counts']['imbalance']:.3f})",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def serve(a, bh, ctx, torch):
     """Serving leg: Poisson arrivals of simulation requests through the continuous-batching server."""
     import numpy as np
@@ -362,13 +398,14 @@ def main():
         del buf
         st = tree.forces_stats()
         torch.cuda.synchronize()
+        shards = one_gpu_share(a, tree, st, stream, torch, ms_walk) if a.shards > 1 else None
         tot = st["totals"]
         inter = int(tot["n_mono"] + tot["n_p2p"])
         results[prec] = dict(ms_per_step=ms_step, ms_walk=ms_walk, ms_build_upward=ms_build,
                              interactions=inter, visits=int(tot["n_visits"]), fallbacks=int(tot["n_fallback"]),
                              wave_visits=int(tot["wave_visits"]), wave_entries=int(tot["wave_entries"]),
                              wave_accepts=int(tot["wave_accepts"]), wave_leaves=int(tot["wave_leaves"]),
-                             acc=st["acc"].cpu().numpy(), lists=lists)
+                             acc=st["acc"].cpu().numpy(), lists=lists, shards=shards)
         print(f"# {prec}: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, build+upward {ms_build:.3f} ms, "
               f"{inter / a.n:.1f} interactions/particle", file=sys.stderr, flush=True)
         del sim, tree
@@ -408,6 +445,8 @@ def main():
     }
     if r.get("lists"):
         out["two_phase_lists"] = r["lists"]
+    if r.get("shards"):
+        out["one_gpu_share"] = r["shards"]
     for prec, rr in results.items():
         if prec == head:
             continue
@@ -420,6 +459,8 @@ def main():
                                   "frac": ach / pk}}
         if rr.get("lists"):
             out[prec]["two_phase_lists"] = rr["lists"]
+        if rr.get("shards"):
+            out[prec]["one_gpu_share"] = rr["shards"]
 
     if a.serve_requests > 0:
         out["serving"] = serve(a, bh, ctx, torch)

@@ -78,6 +78,8 @@ _SIGS = {
     "bh_lists_forces": ([_VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_forces": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_forces_stats": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)], C.c_int),
+    "bh_forces_range": ([_VP, _VP, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP], C.c_int),
+    "bh_shard_bounds": ([_VP, _VP, _VP, _VP, C.c_int32, _VP], C.c_int),
     "bh_tree_info": ([_VP, _VP, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
     "bh_tree_export": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_tree_free": ([_VP, _VP], C.c_int),
@@ -272,6 +274,23 @@ class Tree:
                                      C.byref(st)))
         return dict(acc=acc, pot=ph, n_mono=nm, n_p2p=np_, hash=hs,
                     totals={k: int(getattr(st, k)) for k, _ in Stats._fields_})
+
+    def forces_range(self, first, count, acc=None, pot=None, n_mono=None, n_p2p=None):
+        """bh_forces_range: rows of the bodies of sorted ranks [first, first + count) in acc (and pot,
+        n_mono, n_p2p when given); the other rows keep their contents.  Returns acc."""
+        torch = _torch()
+        if acc is None:
+            acc = torch.full((self.n, 3), float("nan"), dtype=torch.float64, device=self.pos.device)
+        _check(lib().bh_forces_range(self.ctx.h, self.h, int(first), int(count), _ptr(acc), _ptr(pot),
+                                     _ptr(n_mono), _ptr(n_p2p)))
+        return acc
+
+    def shard_bounds(self, G, n_mono=None, n_p2p=None):
+        """bh_shard_bounds: G + 1 int64 range starts (device) for costs 1 + n_mono + n_p2p."""
+        torch = _torch()
+        b = torch.empty(max(int(G) + 1, 1), dtype=torch.int64, device=self.pos.device)   # G < 1: the call refuses it
+        _check(lib().bh_shard_bounds(self.ctx.h, self.h, _ptr(n_mono), _ptr(n_p2p), int(G), _ptr(b)))
+        return b
 
     def info(self):
         nn = C.c_int64()

@@ -1,0 +1,117 @@
+// Cost-balanced split of a tree's bodies into Morton-contiguous target ranges.
+//
+// The paper names the varying work per particle and the tree rebuilt at every
+// step as the obstacles to static load balance (section 1).  The split here is
+// the cost-zone method (Singh, Holt, Totsuka, Gupta and Hennessy, 1995) on the
+// Morton order of the current tree: every body costs one plus the interactions
+// it had in a previous walk, and range j of G starts at the first rank r whose
+// exclusive prefix cost P(r) reaches j/G of the total T (smallest r with
+// G P(r) >= j T; P(0) = 0, so range 0 starts at 0 and range G at n).
+//
+// Three launches: prefix sums within chunks of kShardChunk ranks, a scan of the
+// chunk totals, then one binary search per boundary over P(r) =
+// chunk_prefix[(r - 1) / kShardChunk] + local[r - 1].
+#include "bh_common.h"
+
+namespace bh {
+
+constexpr uint32_t kShardChunk = 1024;   // ranks per chunk: 256 threads x 4
+
+__device__ __forceinline__ unsigned long long body_cost(const uint32_t *idx, const int64_t *nm, const int64_t *np,
+                                                        uint32_t s) {
+    const uint32_t i = idx[s];
+    unsigned long long c = 1;
+    if (nm) c += (unsigned long long)nm[i];
+    if (np) c += (unsigned long long)np[i];
+    return c;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x, int lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// loc[s] = sum of the costs from the start of s's chunk through s; csum[c] = chunk c's total.
+__global__ void __launch_bounds__(256) k_shard_local(const uint32_t *idx, const int64_t *nm, const int64_t *np,
+                                                     uint32_t n, unsigned long long *loc, unsigned long long *csum) {
+    __shared__ unsigned long long wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t base = blockIdx.x * kShardChunk + 4 * threadIdx.x;
+    unsigned long long c[4], run = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        run += base + q < n ? body_cost(idx, nm, np, base + q) : 0ull;
+        c[q] = run;
+    }
+    const unsigned long long x = wave_incl_scan(run, lane);
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    unsigned long long wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    const unsigned long long pre = wpre + x - run;   // costs of this chunk before this thread's ranks
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (base + q < n) loc[base + q] = pre + c[q];
+    if (threadIdx.x == 255) csum[blockIdx.x] = wpre + x;
+}
+
+// Exclusive scan of the nc chunk totals in place; csum[nc] = T.
+__global__ void __launch_bounds__(1024) k_shard_scan(unsigned long long *csum, uint32_t nc) {
+    __shared__ unsigned long long wsum[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long carry = 0;
+    for (uint32_t b = 0; b < nc; b += 1024) {
+        const uint32_t t = b + threadIdx.x;
+        const unsigned long long v = t < nc ? csum[t] : 0ull;
+        const unsigned long long x = wave_incl_scan(v, lane);
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        unsigned long long wpre = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (t < nc) csum[t] = carry + wpre + x - v;
+        carry += tot;
+        __syncthreads();   // wsum is rewritten by the next round
+    }
+    if (threadIdx.x == 0) csum[nc] = carry;
+}
+
+// bounds[j] = smallest r in [0, n] with G P(r) >= j T (j = 0..G).
+__global__ void __launch_bounds__(256) k_shard_search(const unsigned long long *loc, const unsigned long long *csum,
+                                                      uint32_t n, uint32_t nc, uint32_t G, int64_t *bounds) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j > G) return;
+    if (j == 0) {
+        bounds[0] = 0;
+        return;
+    }
+    const unsigned __int128 want = (unsigned __int128)j * csum[nc];
+    uint32_t lo = 1, hi = n;   // P(n) = T, so r = n always qualifies
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const unsigned long long P = csum[(mid - 1) / kShardChunk] + loc[mid - 1];
+        if ((unsigned __int128)G * P >= want) hi = mid;
+        else lo = mid + 1;
+    }
+    bounds[j] = lo;
+}
+
+hipError_t launch_shard_bounds(const ForestDev &f, uint32_t n, const int64_t *n_mono, const int64_t *n_p2p,
+                               uint32_t G, int64_t *bounds, hipStream_t s) {
+    const uint32_t nc = (n + kShardChunk - 1) / kShardChunk;
+    // scratch: the sort's alternate keys (n values) and the bounding-box tile table
+    // (6 per 4096 bodies >= nc + 1 values), both idle between builds
+    unsigned long long *loc = reinterpret_cast<unsigned long long *>(f.keys_alt);
+    unsigned long long *csum = f.tile_mm;
+    hipLaunchKernelGGL(k_shard_local, dim3(nc), dim3(256), 0, s, f.idx, n_mono, n_p2p, n, loc, csum);
+    hipLaunchKernelGGL(k_shard_scan, dim3(1), dim3(1024), 0, s, csum, nc);
+    hipLaunchKernelGGL(k_shard_search, dim3((G + 256) / 256), dim3(256), 0, s, loc, csum, n, nc, G, bounds);
+    return hipGetLastError();
+}
+
+}  // namespace bh

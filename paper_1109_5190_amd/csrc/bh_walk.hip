@@ -73,6 +73,7 @@ struct WalkOut {
     double *acc, *pot;
     int64_t *n_mono, *n_p2p;
     uint64_t *hash;
+    uint32_t wlo = 0, whi = 0xffffffffu;   // bodies written and counted: sorted ranks [wlo, whi)
 };
 
 struct WaveLds32 {
@@ -397,7 +398,8 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     }
     flush_leaves();
     fold();
-    if (live) {
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
@@ -416,8 +418,8 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(live ? nmono : 0), b = wave_sum_u(live ? np2p : 0);
-        unsigned long long v = wave_sum_u(live ? nvis : 0), fb = wave_sum_u(live ? nfb : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0), fb = wave_sum_u(own ? nfb : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);
             atomicAdd(&f.stats[1], b);
@@ -606,7 +608,8 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
         }
     }
     flush_leaves();
-    if (live) {
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
@@ -625,8 +628,8 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(live ? nmono : 0), b = wave_sum_u(live ? np2p : 0);
-        unsigned long long v = wave_sum_u(live ? nvis : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);
             atomicAdd(&f.stats[1], b);
@@ -851,7 +854,8 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
     }
     flush_leaves();
     fold();
-    if (live) {
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
@@ -870,8 +874,8 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(live ? nmono : 0), b = wave_sum_u(live ? np2p : 0);
-        unsigned long long v = wave_sum_u(live ? nvis : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);
             atomicAdd(&f.stats[1], b);
@@ -1027,7 +1031,8 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
         }
     }
     flush_leaves();
-    if (live) {
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
@@ -1046,8 +1051,8 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(live ? nmono : 0), b = wave_sum_u(live ? np2p : 0);
-        unsigned long long v = wave_sum_u(live ? nvis : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);
             atomicAdd(&f.stats[1], b);
@@ -1733,8 +1738,8 @@ static void launch_walk_w(const ForestDev &f, bool want_pot, const WalkOut &o, h
 }
 
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
-                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves) {
-    WalkOut o{acc, pot, n_mono, n_p2p, hash};
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves, uint32_t wlo, uint32_t whi) {
+    WalkOut o{acc, pot, n_mono, n_p2p, hash, wlo, whi};
     if (f.ngroups == 0) return hipSuccess;
     if (stats) {   // the counting walks use one launch shape
         if (want_pot) launch_walk_sp<true, true, 4>(f, o, s);
