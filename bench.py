@@ -236,8 +236,9 @@ def batch(a, bh, torch):
 
 def one_gpu_share(a, tree, st, stream, torch, ms_walk):
     """The walk of one GPU's share when the targets are split G ways (each GPU holding the whole
-    tree): ranges from the cost zones of the counts `st` of a previous walk, and from equal counts,
-    each walked alone on the whole GPU.  The ranges together reproduce the full walk's bits."""
+    tree): ranges from the cost zones of a previous counting walk (interaction counts `st`, or
+    each group's wavefront work) and from equal counts, each range walked alone on the whole GPU.
+    The ranges together reproduce the full walk's bits."""
     G = a.shards
     out = {"G": G}
     b0, b1 = _events(torch)
@@ -248,7 +249,11 @@ def one_gpu_share(a, tree, st, stream, torch, ms_walk):
     torch.cuda.synchronize()
     out["bounds_ms"] = b0.elapsed_time(b1) / a.walk_reps
     acc = torch.empty_like(st["acc"])
-    for name, bl in (("cost_zones", bounds.cpu().tolist()), ("equal_counts", tree.shard_bounds(G).cpu().tolist())):
+    work = torch.empty(tree.n, dtype=torch.int64, device=acc.device)
+    tree.forces_range(0, tree.n, acc, None, None, None, work)   # counting walk: wavefront work per body
+    splits = (("cost_zones", bounds), ("work_zones", tree.shard_bounds(G, work)),
+              ("equal_counts", tree.shard_bounds(G)))
+    for name, bl in ((k, b.cpu().tolist()) for k, b in splits):
         ms = []
         for j in range(G):
             tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
@@ -262,10 +267,8 @@ def one_gpu_share(a, tree, st, stream, torch, ms_walk):
         out[name] = {"ms": ms, "max_ms": max(ms), "sum_ms": sum(ms), "imbalance": max(ms) * G / sum(ms),
                      "full_walk_over_G_vs_max": ms_walk / G / max(ms),
                      "bitwise_equal_to_walk": bool(torch.equal(acc, st["acc"]))}
-    print(f"# one GPU's share of {G}: cost zones max {out['cost_zones']['max_ms']:.3f} ms "
-          f"(imbalance {out['cost_zones']['imbalance']:.3f}), equal counts max "
-          f"{out['equal_counts']['max_ms']:.3f} ms (imbalance {out['equal_counts']['imbalance']:.3f})",
-          file=sys.stderr, flush=True)
+    print(f"# one GPU's share of {G} (max ms, imbalance): " + ", ".join(
+        f"{k} {out[k]['max_ms']:.3f} {out[k]['imbalance']:.3f}" for k, _ in splits), file=sys.stderr, flush=True)
     return out
 
 
@@ -312,8 +315,8 @@ def serve(a, bh, ctx, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
-                                   "(sharding across GPUs is not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (no collectives are "
+                                   "built; the one_gpu_share leg times one GPU's share of a split)"}))
         sys.exit(2)
     import numpy as np
     import torch

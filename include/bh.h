@@ -184,30 +184,35 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, 
 /* bh_forces for the bodies of sorted (Morton) ranks [first, first + count)
  * only: one GPU's share when the targets of one simulation are split across
  * GPUs that each hold the whole tree.  The rows of those bodies in acc (and
- * pot, n_mono, n_p2p when given; caller's order, as bh_forces and
+ * pot, n_mono, n_p2p, work when given; caller's order, as bh_forces and
  * bh_forces_stats write them) receive bh_forces's values bit for bit; every
- * other row is left as it was.  n_mono and n_p2p (device, n each, nullable)
- * request the counting walk, whose counts feed bh_shard_bounds.  The walk
- * runs the 64-body groups that meet the range (section 3: force stage), so
- * a range costs its share of the walk plus at most two partial groups.
- * Sorted rank r is body perm[r] of bh_tree_export.  0 <= first, 0 <= count,
- * first + count <= n, else BH_E_INVAL; count == 0 does nothing.
- * Asynchronous. */
+ * other row is left as it was.  n_mono, n_p2p and work (device, n int64
+ * each, nullable) request the counting walk: interaction counts as
+ * bh_forces_stats gives them, and work, the wavefront work of the body's walk
+ * group (children tested plus pair iterations of the 64-body group's shared
+ * traversal) spread evenly over the group's bodies (body k of c gets
+ * floor(W (k+1) / c) - floor(W k / c), so a group's rows sum to its W).
+ * Either feeds bh_shard_bounds.  The walk runs the 64-body groups that meet
+ * the range (section 3: force stage), so a range costs its share of the walk
+ * plus at most two partial groups.  Sorted rank r is body perm[r] of
+ * bh_tree_export.  0 <= first, 0 <= count, first + count <= n, else
+ * BH_E_INVAL; count == 0 does nothing.  Asynchronous. */
 bh_status bh_forces_range(bh_ctx *ctx, bh_tree *tree, int64_t first, int64_t count, double *acc, double *pot,
-                          int64_t *n_mono, int64_t *n_p2p);
+                          int64_t *n_mono, int64_t *n_p2p, int64_t *work);
 
 /* Split of the tree's n bodies into G Morton-contiguous target ranges of equal
  * cost (section 1 names the per-particle work, which varies and changes with
  * every rebuilt tree, as what defeats static splits; this is the cost-zone
- * method of Singh et al., 1995).  Body i costs 1 + n_mono[i] + n_p2p[i]
- * (device, n each, caller's order, from a counting walk of a previous step;
- * either nullable: its term is 0, both null: equal counts).  With P(r) the
- * summed cost of the bodies of sorted ranks below r and T = P(n), bounds
- * (device, G + 1 int64) receives, for j = 0..G, the smallest r with
- * G P(r) >= j T: range j is [bounds[j], bounds[j + 1]), bounds[0] = 0,
- * bounds[G] = n.  Uses the tree's build scratch (the tree stays valid);
- * 1 <= G <= 65536, else BH_E_INVAL.  Asynchronous. */
-bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *tree, const int64_t *n_mono, const int64_t *n_p2p, int32_t G,
+ * method of Singh et al., 1995).  Body i costs 1 + cost_a[i] + cost_b[i]
+ * (device, n int64 each, caller's order, from a counting walk of a previous
+ * step: n_mono and n_p2p, or work and NULL; a null array contributes 0, both
+ * null give equal counts).  With P(r) the summed cost of the bodies of sorted
+ * ranks below r and T = P(n), bounds (device, G + 1 int64) receives, for
+ * j = 0..G, the smallest r with G P(r) >= j T: range j is
+ * [bounds[j], bounds[j + 1]), bounds[0] = 0, bounds[G] = n.  Uses the tree's
+ * build scratch (the tree stays valid); 1 <= G <= 65536, else BH_E_INVAL.
+ * Asynchronous. */
+bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *tree, const int64_t *cost_a, const int64_t *cost_b, int32_t G,
                           int64_t *bounds);
 
 /* ------------------------------------------------------ interaction lists --- */

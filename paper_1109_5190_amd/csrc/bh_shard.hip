@@ -3,8 +3,9 @@
 // The paper names the varying work per particle and the tree rebuilt at every
 // step as the obstacles to static load balance (section 1).  The split here is
 // the cost-zone method (Singh, Holt, Totsuka, Gupta and Hennessy, 1995) on the
-// Morton order of the current tree: every body costs one plus the interactions
-// it had in a previous walk, and range j of G starts at the first rank r whose
+// Morton order of the current tree: every body costs one plus what a previous
+// counting walk measured for it (its interactions, or its share of its group's
+// wavefront work), and range j of G starts at the first rank r whose
 // exclusive prefix cost P(r) reaches j/G of the total T (smallest r with
 // G P(r) >= j T; P(0) = 0, so range 0 starts at 0 and range G at n).
 //
@@ -17,12 +18,12 @@ namespace bh {
 
 constexpr uint32_t kShardChunk = 1024;   // ranks per chunk: 256 threads x 4
 
-__device__ __forceinline__ unsigned long long body_cost(const uint32_t *idx, const int64_t *nm, const int64_t *np,
+__device__ __forceinline__ unsigned long long body_cost(const uint32_t *idx, const int64_t *ca, const int64_t *cb,
                                                         uint32_t s) {
     const uint32_t i = idx[s];
     unsigned long long c = 1;
-    if (nm) c += (unsigned long long)nm[i];
-    if (np) c += (unsigned long long)np[i];
+    if (ca) c += (unsigned long long)ca[i];
+    if (cb) c += (unsigned long long)cb[i];
     return c;
 }
 
@@ -35,7 +36,7 @@ __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long 
 }
 
 // loc[s] = sum of the costs from the start of s's chunk through s; csum[c] = chunk c's total.
-__global__ void __launch_bounds__(256) k_shard_local(const uint32_t *idx, const int64_t *nm, const int64_t *np,
+__global__ void __launch_bounds__(256) k_shard_local(const uint32_t *idx, const int64_t *ca, const int64_t *cb,
                                                      uint32_t n, unsigned long long *loc, unsigned long long *csum) {
     __shared__ unsigned long long wsum[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -43,7 +44,7 @@ __global__ void __launch_bounds__(256) k_shard_local(const uint32_t *idx, const 
     unsigned long long c[4], run = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        run += base + q < n ? body_cost(idx, nm, np, base + q) : 0ull;
+        run += base + q < n ? body_cost(idx, ca, cb, base + q) : 0ull;
         c[q] = run;
     }
     const unsigned long long x = wave_incl_scan(run, lane);
@@ -101,14 +102,14 @@ __global__ void __launch_bounds__(256) k_shard_search(const unsigned long long *
     bounds[j] = lo;
 }
 
-hipError_t launch_shard_bounds(const ForestDev &f, uint32_t n, const int64_t *n_mono, const int64_t *n_p2p,
+hipError_t launch_shard_bounds(const ForestDev &f, uint32_t n, const int64_t *cost_a, const int64_t *cost_b,
                                uint32_t G, int64_t *bounds, hipStream_t s) {
     const uint32_t nc = (n + kShardChunk - 1) / kShardChunk;
     // scratch: the sort's alternate keys (n values) and the bounding-box tile table
     // (6 per 4096 bodies >= nc + 1 values), both idle between builds
     unsigned long long *loc = reinterpret_cast<unsigned long long *>(f.keys_alt);
     unsigned long long *csum = f.tile_mm;
-    hipLaunchKernelGGL(k_shard_local, dim3(nc), dim3(256), 0, s, f.idx, n_mono, n_p2p, n, loc, csum);
+    hipLaunchKernelGGL(k_shard_local, dim3(nc), dim3(256), 0, s, f.idx, cost_a, cost_b, n, loc, csum);
     hipLaunchKernelGGL(k_shard_scan, dim3(1), dim3(1024), 0, s, csum, nc);
     hipLaunchKernelGGL(k_shard_search, dim3((G + 256) / 256), dim3(256), 0, s, loc, csum, n, nc, G, bounds);
     return hipGetLastError();

@@ -74,6 +74,7 @@ struct WalkOut {
     int64_t *n_mono, *n_p2p;
     uint64_t *hash;
     uint32_t wlo = 0, whi = 0xffffffffu;   // bodies written and counted: sorted ranks [wlo, whi)
+    int64_t *work = nullptr;               // counting walks: the group's wavefront work per body
 };
 
 struct WaveLds32 {
@@ -165,8 +166,10 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         }
     };
     // queued leaf particles: load and convert lane-parallel, then one pass per particle
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
     auto flush_leaves = [&]() {
         if (qn == 0) return;
+        if (STATS) wwork += qn;
         if (work + qn > kFlushWork) fold();
         work += qn;
         if (!SOFT) {
@@ -249,6 +252,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         --sp;
         const uint4 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
         if ((uint32_t)lane < nch) {
@@ -415,6 +419,10 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
             if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
         }
     }
     if (STATS) {
@@ -485,8 +493,10 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
             if (POT) ap -= mr;
         }
     };
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
     auto flush_leaves = [&]() {
         if (qn == 0) return;
+        if (STATS) wwork += qn;
         for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
             const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
             wave_sync();
@@ -521,6 +531,7 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
         --sp;
         const uint4 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
         if ((uint32_t)lane < nch) {
@@ -625,6 +636,10 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
             if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
         }
     }
     if (STATS) {
@@ -733,8 +748,10 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
         if (POT) { kahan_add(sp_, cp, ap); ap = 0.f; }
         work = 0;
     };
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
     auto flush_leaves = [&]() {
         if (qn == 0) return;
+        if (STATS) wwork += qn;
         if (work + qn > kFlushWork) fold();
         work += qn;
         for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
@@ -786,6 +803,7 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
         --sp;
         const uint2 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
         wave_sync();
         bool acc_c = false;
         if ((uint32_t)lane < nch) {
@@ -871,6 +889,10 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
             if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
         }
     }
     if (STATS) {
@@ -931,8 +953,10 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
     uint32_t nmono = 0, np2p = 0, nvis = 0;
     uint64_t h = 0;
     uint32_t qn = 0;
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
     auto flush_leaves = [&]() {
         if (qn == 0) return;
+        if (STATS) wwork += qn;
         wave_sync();
         if ((uint32_t)lane < qn) {
             const size_t j = L.irank[lane];
@@ -973,6 +997,7 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
         --sp;
         const uint2 e = L.stk[sp];
         const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
         wave_sync();
         bool acc_c = false;
         if ((uint32_t)lane < nch) {
@@ -1048,6 +1073,10 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
             if (out.n_mono) out.n_mono[i] = nmono;
             if (out.n_p2p) out.n_p2p[i] = np2p;
             if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
         }
     }
     if (STATS) {
@@ -1738,8 +1767,9 @@ static void launch_walk_w(const ForestDev &f, bool want_pot, const WalkOut &o, h
 }
 
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
-                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves, uint32_t wlo, uint32_t whi) {
-    WalkOut o{acc, pot, n_mono, n_p2p, hash, wlo, whi};
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves, uint32_t wlo, uint32_t whi,
+                       int64_t *work) {
+    WalkOut o{acc, pot, n_mono, n_p2p, hash, wlo, whi, work};
     if (f.ngroups == 0) return hipSuccess;
     if (stats) {   // the counting walks use one launch shape
         if (want_pot) launch_walk_sp<true, true, 4>(f, o, s);

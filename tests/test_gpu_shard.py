@@ -1,8 +1,10 @@
 """One GPU's target share (bh_forces_range) and the cost-balanced split of the targets
 (bh_shard_bounds).  A range walk writes the full walk's bits on the rows of its bodies and
-leaves every other row as it was, for each kind of tree; the ranges of a split together give
-the full walk; the split equals the cost-zone definition (smallest rank r with G P(r) >= j T)
-evaluated with numpy from the same counts, over ragged sizes and more than 1024 chunks."""
+leaves every other row as it was, for each kind of tree; the per-body work output is each
+group's wavefront work spread evenly and sums to the walk's wavefront totals; the ranges of a
+split together give the full walk; the split equals the cost-zone definition (smallest rank r
+with G P(r) >= j T) evaluated with numpy from the same costs, over ragged sizes and more than
+1024 chunks."""
 import numpy as np
 import pytest
 
@@ -55,6 +57,8 @@ def test_range_rows_are_the_full_walks(ctx, var, eps):
     t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.6, eps, **VARIANTS[var])).upward()
     full, pfull = t.forces(pot=True)
     st = t.forces_stats()
+    wfull = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wfull)
     perm = t.export(with_mass=False)["perm"].long()
     for first, count in RANGES:
         first = n - 37 if first is None else first
@@ -68,12 +72,39 @@ def test_range_rows_are_the_full_walks(ctx, var, eps):
         assert torch.isnan(acc[other]).all() and torch.isnan(pot[other]).all(), (first, count)
         # the counting walk over the same range
         acc2 = nan_like(n, 3)
-        nm = torch.full((n,), -1, dtype=torch.int64, device="cuda")
-        np_ = torch.full((n,), -1, dtype=torch.int64, device="cuda")
-        t.forces_range(first, count, acc2, None, nm, np_)
+        nm, np_, wk = (torch.full((n,), -1, dtype=torch.int64, device="cuda") for _ in range(3))
+        t.forces_range(first, count, acc2, None, nm, np_, wk)
         assert torch.equal(acc2[rows], st["acc"][rows])
         assert torch.equal(nm[rows], st["n_mono"][rows]) and torch.equal(np_[rows], st["n_p2p"][rows])
-        assert (nm[other] == -1).all() and (np_[other] == -1).all() and torch.isnan(acc2[other]).all()
+        assert torch.equal(wk[rows], wfull[rows])
+        assert (nm[other] == -1).all() and (np_[other] == -1).all() and (wk[other] == -1).all()
+        assert torch.isnan(acc2[other]).all()
+
+
+@pytest.mark.parametrize("var", ["fp32", "fp64", "fp32-group", "fp64-group", "fp32-quad"])
+def test_work_is_the_groups_wavefront_work(ctx, var):
+    """Each 64-body group's work W (children tested plus pair iterations of its shared
+    traversal) spread evenly over its bodies; with one particle per leaf every opened leaf is
+    one pair iteration, so the FP32 walks' totals give sum W = wavefront visits + opened leaves."""
+    n = 6000
+    s = icgen.plummer(n, 17)
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.6, 0.01, **VARIANTS[var])).upward()
+    wk = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wk)
+    perm = t.export(with_mass=False)["perm"].long()
+    ws = wk[perm].cpu().numpy()
+    assert ws.min() >= 0
+    W = []
+    for g in range(0, n, 64):
+        v = ws[g:g + 64]
+        c, Wg = len(v), int(v.sum())
+        k = np.arange(c)
+        assert np.array_equal(v, (Wg * (k + 1)) // c - (Wg * k) // c), g
+        W.append(Wg)
+    assert min(W) > 0
+    if var.startswith("fp32"):
+        tot = t.forces_stats()["totals"]
+        assert sum(W) == tot["wave_visits"] + tot["wave_leaves"]
 
 
 @pytest.mark.parametrize("G", [1, 2, 3, 8, 64, 1000])
@@ -94,6 +125,10 @@ def test_bounds_are_the_cost_zones(ctx, G):
     # one count array, and none (equal counts: ceil(j n / G))
     c1 = (1 + nm.cpu().numpy())[perm]
     assert np.array_equal(t.shard_bounds(G, nm, None).cpu().numpy(), cost_zones(c1, G))
+    wk = torch.empty(n, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wk)
+    cw = (1 + wk.cpu().numpy())[perm]
+    assert np.array_equal(t.shard_bounds(G, wk).cpu().numpy(), cost_zones(cw, G))
     eq = np.array([-(-j * n // G) for j in range(G + 1)], dtype=np.int64)
     assert np.array_equal(t.shard_bounds(G).cpu().numpy(), eq)
 
@@ -120,11 +155,14 @@ def test_shards_cover_the_full_walk(ctx):
     for prec in ("fp32", "fp64"):
         t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.5, 0.005, precision=prec)).upward()
         st = t.forces_stats()
-        b = t.shard_bounds(8, st["n_mono"], st["n_p2p"]).cpu().tolist()
-        acc = nan_like(n, 3)
-        for j in range(8):
-            t.forces_range(b[j], b[j + 1] - b[j], acc)
-        assert torch.equal(acc, st["acc"]), prec
+        wk = torch.empty(n, dtype=torch.int64, device="cuda")
+        t.forces_range(0, n, None, None, None, None, wk)
+        for b in (t.shard_bounds(8, st["n_mono"], st["n_p2p"]), t.shard_bounds(8, wk)):
+            b = b.cpu().tolist()
+            acc = nan_like(n, 3)
+            for j in range(8):
+                t.forces_range(b[j], b[j + 1] - b[j], acc)
+            assert torch.equal(acc, st["acc"]), prec
 
 
 def test_arguments_validated(ctx):
