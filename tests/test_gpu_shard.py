@@ -181,3 +181,31 @@ def test_arguments_validated(ctx):
             t.shard_bounds(G)
     acc = t.forces_range(300, 0)                # empty range at the end: nothing written
     assert torch.isnan(acc).all()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130])
+def test_tiny_trees(ctx, n):
+    """Trees of one partial group up to a few groups; every single-body range, and splits with
+    more ranges than bodies (empty ranges where a boundary repeats)."""
+    print(f"[tiny] n={n}", flush=True)
+    s = icgen.plummer(max(n, 2), 18)
+    pos, mass = s.pos[:n], s.mass[:n]
+    for prec in ("fp32", "fp64"):
+        t = bh.Tree(ctx, dev(pos), dev(mass), bh.params(0.5, 0.01, precision=prec)).upward()
+        st = t.forces_stats()
+        perm = t.export(with_mass=False)["perm"].long()
+        acc = nan_like(n, 3)
+        for r in range(n):
+            t.forces_range(r, 1, acc)
+            assert torch.equal(acc[perm[r]], st["acc"][perm[r]]), (prec, r)
+        assert torch.equal(acc, st["acc"])
+        wk = torch.empty(n, dtype=torch.int64, device="cuda")
+        t.forces_range(0, n, None, None, None, None, wk)
+        ps = perm.cpu().numpy()
+        for G in (1, 3, 2 * n + 1):
+            b = t.shard_bounds(G, wk).cpu().numpy()
+            assert np.array_equal(b, cost_zones((1 + wk.cpu().numpy())[ps], G)), (prec, G)
+            acc2 = nan_like(n, 3)
+            for j in range(G):
+                t.forces_range(int(b[j]), int(b[j + 1] - b[j]), acc2)
+            assert torch.equal(acc2, st["acc"]), (prec, G)
