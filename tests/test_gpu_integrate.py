@@ -154,3 +154,32 @@ def test_autotune_changes_no_result(ctx):
     ref.step(2, 1e-3)
     ctx.sync()
     assert torch.equal(fo.pos, ref.pos) and torch.equal(fo.acc, ref.acc)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_split_and_resumed_runs_are_bit_identical(ctx, prec):
+    """Checkpoint and resume: a simulation views caller memory, so its state is (pos, vel); six
+    steps in one call, three + three calls on one simulation (the fused kick-kick between steps
+    against a closing and an opening kick), and three steps, a copy of (pos, vel) into new
+    tensors and three steps of a new simulation all give the same bits (the first force
+    evaluation of the resumed run is the walk the first run did at the same positions)."""
+    s = icgen.plummer(12000, 19)
+    p = bh.params(0.5, 0.01, precision=prec)
+    runs = []
+    for split in ("one", "two", "resume"):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        sim = bh.Sim(ctx, pos, vel, mass, p)
+        if split == "one":
+            sim.step(6, 1e-3)
+        else:
+            sim.step(3, 1e-3)
+            if split == "resume":
+                pos, vel = pos.clone(), vel.clone()
+                sim.close()
+                sim = bh.Sim(ctx, pos, vel, mass, p)
+            sim.step(3, 1e-3)
+        ctx.sync()
+        runs.append((pos, vel, sim.acc))
+    for k in (1, 2):
+        for a, b in zip(runs[0], runs[k]):
+            assert torch.equal(a, b), k
