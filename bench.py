@@ -236,8 +236,9 @@ def batch(a, bh, torch):
 
 def one_gpu_share(a, tree, st, stream, torch, ms_walk):
     """The walk of one GPU's share when the targets are split G ways (each GPU holding the whole
-    tree): ranges from the cost zones of a previous counting walk (interaction counts `st`, or
-    each group's wavefront work) and from equal counts, each range walked alone on the whole GPU.
+    tree): ranges from the cost zones of a previous counting walk (interaction counts `st`, each
+    group's wavefront work spread over its bodies, or the same work per group with ranges on group
+    boundaries) and from equal counts, each range walked alone on the whole GPU.
     The ranges together reproduce the full walk's bits."""
     G = a.shards
     out = {"G": G}
@@ -250,8 +251,16 @@ def one_gpu_share(a, tree, st, stream, torch, ms_walk):
     out["bounds_ms"] = b0.elapsed_time(b1) / a.walk_reps
     acc = torch.empty_like(st["acc"])
     work = torch.empty(tree.n, dtype=torch.int64, device=acc.device)
-    tree.forces_range(0, tree.n, acc, None, None, None, work)   # counting walk: wavefront work per body
-    splits = (("cost_zones", bounds), ("work_zones", tree.shard_bounds(G, work)),
+    gwork = torch.empty((tree.n + 63) // 64, dtype=torch.int64, device=acc.device)
+    tree.forces_range(0, tree.n, acc, None, None, None, work, gwork)   # counting walk: wavefront work
+    torch.cuda.synchronize()
+    b0.record(stream)
+    for _ in range(a.walk_reps):
+        gbounds = tree.shard_bounds_groups(G, gwork)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    out["bounds_groups_ms"] = b0.elapsed_time(b1) / a.walk_reps
+    splits = (("cost_zones", bounds), ("work_zones", tree.shard_bounds(G, work)), ("group_zones", gbounds),
               ("equal_counts", tree.shard_bounds(G)))
     for name, bl in ((k, b.cpu().tolist()) for k, b in splits):
         ms = []

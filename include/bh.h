@@ -186,19 +186,21 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *tree, double *acc, double *pot, 
  * GPUs that each hold the whole tree.  The rows of those bodies in acc (and
  * pot, n_mono, n_p2p, work when given; caller's order, as bh_forces and
  * bh_forces_stats write them) receive bh_forces's values bit for bit; every
- * other row is left as it was.  n_mono, n_p2p and work (device, n int64
- * each, nullable) request the counting walk: interaction counts as
- * bh_forces_stats gives them, and work, the wavefront work of the body's walk
- * group (children tested plus pair iterations of the 64-body group's shared
- * traversal) spread evenly over the group's bodies (body k of c gets
- * floor(W (k+1) / c) - floor(W k / c), so a group's rows sum to its W).
- * Either feeds bh_shard_bounds.  The walk runs the 64-body groups that meet
- * the range (section 3: force stage), so a range costs its share of the walk
- * plus at most two partial groups.  Sorted rank r is body perm[r] of
- * bh_tree_export.  0 <= first, 0 <= count, first + count <= n, else
- * BH_E_INVAL; count == 0 does nothing.  Asynchronous. */
+ * other row is left as it was.  n_mono, n_p2p, work (device, n int64 each)
+ * and group_work (device, ceil(n / 64) int64), each nullable, request the
+ * counting walk: interaction counts as bh_forces_stats gives them; group_work,
+ * the wavefront work W of each 64-body walk group (group g: sorted ranks
+ * [64 g, min(64 g + 64, n))), the children tested plus the pair iterations of
+ * the group's shared traversal, written for every group that meets the range;
+ * work, that W spread evenly over the group's bodies (body k of c gets
+ * floor(W (k+1) / c) - floor(W k / c), so a group's rows sum to its W).  They
+ * feed bh_shard_bounds and bh_shard_bounds_groups.  The walk runs the 64-body
+ * groups that meet the range (section 3: force stage), so a range costs its
+ * share of the walk plus at most two partial groups.  Sorted rank r is body
+ * perm[r] of bh_tree_export.  0 <= first, 0 <= count, first + count <= n,
+ * else BH_E_INVAL; count == 0 does nothing.  Asynchronous. */
 bh_status bh_forces_range(bh_ctx *ctx, bh_tree *tree, int64_t first, int64_t count, double *acc, double *pot,
-                          int64_t *n_mono, int64_t *n_p2p, int64_t *work);
+                          int64_t *n_mono, int64_t *n_p2p, int64_t *work, int64_t *group_work);
 
 /* Split of the tree's n bodies into G Morton-contiguous target ranges of equal
  * cost (section 1 names the per-particle work, which varies and changes with
@@ -214,6 +216,16 @@ bh_status bh_forces_range(bh_ctx *ctx, bh_tree *tree, int64_t first, int64_t cou
  * Asynchronous. */
 bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *tree, const int64_t *cost_a, const int64_t *cost_b, int32_t G,
                           int64_t *bounds);
+
+/* The same split over the 64-body walk groups, so that every range starts on a
+ * group boundary and no group is walked by two ranges.  Group g costs its body
+ * count plus group_work[g] (device, ceil(n / 64) int64, rank order, from a
+ * counting walk); with P(m) the summed cost of groups below m and T the
+ * total, bounds[j] (device, G + 1 int64) = min(64 x, n) for the smallest x
+ * with G P(x) >= j T.  The costs are read contiguously (1/64 of the data of
+ * bh_shard_bounds, none of it gathered).  Same scratch, limits and errors as
+ * bh_shard_bounds.  Asynchronous. */
+bh_status bh_shard_bounds_groups(bh_ctx *ctx, bh_tree *tree, const int64_t *group_work, int32_t G, int64_t *bounds);
 
 /* ------------------------------------------------------ interaction lists --- */
 

@@ -78,8 +78,9 @@ _SIGS = {
     "bh_lists_forces": ([_VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_forces": ([_VP, _VP, _VP, _VP], C.c_int),
     "bh_forces_stats": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)], C.c_int),
-    "bh_forces_range": ([_VP, _VP, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "bh_forces_range": ([_VP, _VP, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_shard_bounds": ([_VP, _VP, _VP, _VP, C.c_int32, _VP], C.c_int),
+    "bh_shard_bounds_groups": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int),
     "bh_tree_info": ([_VP, _VP, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
     "bh_tree_export": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "bh_tree_free": ([_VP, _VP], C.c_int),
@@ -275,14 +276,15 @@ class Tree:
         return dict(acc=acc, pot=ph, n_mono=nm, n_p2p=np_, hash=hs,
                     totals={k: int(getattr(st, k)) for k, _ in Stats._fields_})
 
-    def forces_range(self, first, count, acc=None, pot=None, n_mono=None, n_p2p=None, work=None):
+    def forces_range(self, first, count, acc=None, pot=None, n_mono=None, n_p2p=None, work=None, group_work=None):
         """bh_forces_range: rows of the bodies of sorted ranks [first, first + count) in acc (and pot,
-        n_mono, n_p2p, work when given); the other rows keep their contents.  Returns acc."""
+        n_mono, n_p2p, work when given; group_work per 64-body group); the other rows keep their
+        contents.  Returns acc."""
         torch = _torch()
         if acc is None:
             acc = torch.full((self.n, 3), float("nan"), dtype=torch.float64, device=self.pos.device)
         _check(lib().bh_forces_range(self.ctx.h, self.h, int(first), int(count), _ptr(acc), _ptr(pot),
-                                     _ptr(n_mono), _ptr(n_p2p), _ptr(work)))
+                                     _ptr(n_mono), _ptr(n_p2p), _ptr(work), _ptr(group_work)))
         return acc
 
     def shard_bounds(self, G, cost_a=None, cost_b=None):
@@ -290,6 +292,13 @@ class Tree:
         torch = _torch()
         b = torch.empty(max(int(G) + 1, 1), dtype=torch.int64, device=self.pos.device)   # G < 1: the call refuses it
         _check(lib().bh_shard_bounds(self.ctx.h, self.h, _ptr(cost_a), _ptr(cost_b), int(G), _ptr(b)))
+        return b
+
+    def shard_bounds_groups(self, G, group_work):
+        """bh_shard_bounds_groups: G + 1 int64 range starts (device) on 64-body group boundaries."""
+        torch = _torch()
+        b = torch.empty(max(int(G) + 1, 1), dtype=torch.int64, device=self.pos.device)   # G < 1: the call refuses it
+        _check(lib().bh_shard_bounds_groups(self.ctx.h, self.h, _ptr(group_work), int(G), _ptr(b)))
         return b
 
     def info(self):

@@ -512,7 +512,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
 }
 
 bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count, double *acc, double *pot,
-                          int64_t *n_mono, int64_t *n_p2p, int64_t *work) {
+                          int64_t *n_mono, int64_t *n_p2p, int64_t *work, int64_t *group_work) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_range");
     const int64_t n = t->F.dev.ntot;
@@ -524,10 +524,10 @@ bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count,
     const int64_t g0 = first / kGroup, g1 = (first + count + kGroup - 1) / kGroup;
     D.groups += g0;
     D.ngroups = (uint32_t)(g1 - g0);
-    const bool stats = n_mono || n_p2p || work;
+    const bool stats = n_mono || n_p2p || work || group_work;
     if (stats) HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
     HIPCHK(launch_walk(D, stats, pot != nullptr, acc, pot, n_mono, n_p2p, nullptr, ctx->stream, t->F.walk_waves,
-                       (uint32_t)first, (uint32_t)(first + count), work));
+                       (uint32_t)first, (uint32_t)(first + count), work, group_work));
     return BH_OK;
 }
 
@@ -536,7 +536,16 @@ bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *t, const int64_t *cost_a, const 
     if (!ctx || !t || !bounds) return bh_fail(BH_E_INVAL, "NULL argument");
     if (G < 1 || G > 65536) return bh_fail(BH_E_INVAL, "G must be in [1, 65536]");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "the tree must be built (bh_upward) before bh_shard_bounds");
-    HIPCHK(launch_shard_bounds(t->F.dev, t->F.dev.ntot, cost_a, cost_b, (uint32_t)G, bounds, ctx->stream));
+    HIPCHK(launch_shard_bounds(t->F.dev, t->F.dev.ntot, cost_a, cost_b, nullptr, (uint32_t)G, bounds, ctx->stream));
+    return BH_OK;
+}
+
+bh_status bh_shard_bounds_groups(bh_ctx *ctx, bh_tree *t, const int64_t *group_work, int32_t G, int64_t *bounds) {
+    if (!ctx || !t || !group_work || !bounds) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (G < 1 || G > 65536) return bh_fail(BH_E_INVAL, "G must be in [1, 65536]");
+    if (!t->upward_done) return bh_fail(BH_E_INVAL, "the tree must be built (bh_upward) before bh_shard_bounds_groups");
+    HIPCHK(launch_shard_bounds(t->F.dev, t->F.dev.ntot, nullptr, nullptr, group_work, (uint32_t)G, bounds,
+                               ctx->stream));
     return BH_OK;
 }
 

@@ -259,13 +259,17 @@ hipError_t launch_build(const ForestDev &f, const double *pos, const double *mas
                         hipStream_t s);                          // bbox .. tree topology
 hipError_t launch_upward(const ForestDev &f, hipStream_t s);     // masses, centres, walk records
 // Walks the groups of f (a copy may point at a sub-range of them); outputs and
-// totals only for the bodies of sorted ranks [wlo, whi).  work (counting walks,
-// nullable): each body's share of its group's wavefront work.
+// totals only for the bodies of sorted ranks [wlo, whi).  Counting walks, each
+// nullable: work, each body's share of its group's wavefront work; gwork, that
+// work per walk group (indexed by the group's first rank / 64 in its simulation).
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves = 4, uint32_t wlo = 0,
-                       uint32_t whi = 0xffffffffu, int64_t *work = nullptr);
+                       uint32_t whi = 0xffffffffu, int64_t *work = nullptr, int64_t *gwork = nullptr);
+// Cost zones over n bodies: per body (gathered through the sort order from two
+// caller-order arrays) when group_cost is null, else per 64-body walk group (group
+// g costs its body count plus group_cost[g]; bounds on group boundaries).
 hipError_t launch_shard_bounds(const ForestDev &f, uint32_t n, const int64_t *cost_a, const int64_t *cost_b,
-                               uint32_t G, int64_t *bounds, hipStream_t s);
+                               const int64_t *group_cost, uint32_t G, int64_t *bounds, hipStream_t s);
 // phase_mask 0: every simulation; else only those whose SegDesc.phase has a bit of the mask.
 hipError_t launch_kick(const ForestDev &f, double *vel, const double *acc, uint32_t phase_mask, hipStream_t s);
 hipError_t launch_drift(const ForestDev &f, double *pos, const double *vel, uint32_t phase_mask, hipStream_t s);

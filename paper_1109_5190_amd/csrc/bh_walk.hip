@@ -75,6 +75,7 @@ struct WalkOut {
     uint64_t *hash;
     uint32_t wlo = 0, whi = 0xffffffffu;   // bodies written and counted: sorted ranks [wlo, whi)
     int64_t *work = nullptr;               // counting walks: the group's wavefront work per body
+    int64_t *gwork = nullptr;              // counting walks: the wavefront work of each walk group
 };
 
 struct WaveLds32 {
@@ -403,6 +404,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     flush_leaves();
     fold();
     const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
@@ -620,6 +622,7 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     }
     flush_leaves();
     const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
@@ -873,6 +876,7 @@ __global__ void __launch_bounds__(256) k_gwalk32(ForestDev f, WalkOut out) {
     flush_leaves();
     fold();
     const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
@@ -1057,6 +1061,7 @@ __global__ void __launch_bounds__(256) k_gwalk64(ForestDev f, WalkOut out) {
     }
     flush_leaves();
     const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
@@ -1768,8 +1773,8 @@ static void launch_walk_w(const ForestDev &f, bool want_pot, const WalkOut &o, h
 
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves, uint32_t wlo, uint32_t whi,
-                       int64_t *work) {
-    WalkOut o{acc, pot, n_mono, n_p2p, hash, wlo, whi, work};
+                       int64_t *work, int64_t *gwork) {
+    WalkOut o{acc, pot, n_mono, n_p2p, hash, wlo, whi, work, gwork};
     if (f.ngroups == 0) return hipSuccess;
     if (stats) {   // the counting walks use one launch shape
         if (want_pot) launch_walk_sp<true, true, 4>(f, o, s);

@@ -23,3 +23,12 @@ def cost_zones(cost, G):
     P = np.concatenate([[0], np.cumsum(cost, dtype=np.int64)])
     T = int(P[-1])
     return np.array([np.searchsorted(G * P, j * T, side="left") for j in range(G + 1)], dtype=np.int64)
+
+
+def group_zones(group_cost, n, G, group=64):
+    """The split over walk groups of `group` bodies: group g costs its body count plus
+    group_cost[g]; range j starts at min(group x, n) for the smallest group boundary x with
+    G P(x) >= j T."""
+    counts = np.minimum(group, n - group * np.arange(len(group_cost)))
+    x = cost_zones(counts + np.asarray(group_cost, dtype=np.int64), G)
+    return np.minimum(group * x, n)

@@ -2,7 +2,7 @@
 definition and against splits worked by hand.  CPU only."""
 import numpy as np
 
-from tests.costzones import cost_zones, cost_zones_literal
+from tests.costzones import cost_zones, cost_zones_literal, group_zones
 
 
 def test_by_hand():
@@ -20,3 +20,11 @@ def test_search_is_the_definition():
         c = rng.integers(1, 50, n)
         for G in (1, 2, 3, 8, 13, 64):
             assert np.array_equal(cost_zones(c, G), cost_zones_literal(c, G)), (n, G)
+
+
+def test_group_split_by_hand():
+    # 130 bodies in groups of 64, 64 and 2; group costs 10, 0, 0 -> 74, 64, 2 (T = 140)
+    # two ranges: 2 P(x) >= 140 first at x = 1 (P = 74): the split is at rank 64
+    assert group_zones([10, 0, 0], 130, 2).tolist() == [0, 64, 130]
+    # heavy last group: P = 64, 128, 1130; half of T (565) is reached at x = 3 -> rank min(192, 130)
+    assert group_zones([0, 0, 1000], 130, 2).tolist() == [0, 130, 130]

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import icgen
-from tests.costzones import cost_zones
+from tests.costzones import cost_zones, group_zones
 from tests.gpu_helpers import dev
 
 pytestmark = pytest.mark.gpu
@@ -57,8 +57,10 @@ def test_range_rows_are_the_full_walks(ctx, var, eps):
     t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.6, eps, **VARIANTS[var])).upward()
     full, pfull = t.forces(pot=True)
     st = t.forces_stats()
+    ng = (n + 63) // 64
     wfull = torch.full((n,), -1, dtype=torch.int64, device="cuda")
-    t.forces_range(0, n, None, None, None, None, wfull)
+    gfull = torch.full((ng,), -1, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wfull, gfull)
     perm = t.export(with_mass=False)["perm"].long()
     for first, count in RANGES:
         first = n - 37 if first is None else first
@@ -73,7 +75,10 @@ def test_range_rows_are_the_full_walks(ctx, var, eps):
         # the counting walk over the same range
         acc2 = nan_like(n, 3)
         nm, np_, wk = (torch.full((n,), -1, dtype=torch.int64, device="cuda") for _ in range(3))
-        t.forces_range(first, count, acc2, None, nm, np_, wk)
+        gw = torch.full((ng,), -1, dtype=torch.int64, device="cuda")
+        t.forces_range(first, count, acc2, None, nm, np_, wk, gw)
+        g0, g1 = first // 64, (first + count + 63) // 64 if count else first // 64   # groups the range meets
+        assert torch.equal(gw[g0:g1], gfull[g0:g1]) and (gw[:g0] == -1).all() and (gw[g1:] == -1).all()
         assert torch.equal(acc2[rows], st["acc"][rows])
         assert torch.equal(nm[rows], st["n_mono"][rows]) and torch.equal(np_[rows], st["n_p2p"][rows])
         assert torch.equal(wk[rows], wfull[rows])
@@ -90,7 +95,8 @@ def test_work_is_the_groups_wavefront_work(ctx, var):
     s = icgen.plummer(n, 17)
     t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.6, 0.01, **VARIANTS[var])).upward()
     wk = torch.full((n,), -1, dtype=torch.int64, device="cuda")
-    t.forces_range(0, n, None, None, None, None, wk)
+    gw = torch.full(((n + 63) // 64,), -1, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wk, gw)
     perm = t.export(with_mass=False)["perm"].long()
     ws = wk[perm].cpu().numpy()
     assert ws.min() >= 0
@@ -102,6 +108,7 @@ def test_work_is_the_groups_wavefront_work(ctx, var):
         assert np.array_equal(v, (Wg * (k + 1)) // c - (Wg * k) // c), g
         W.append(Wg)
     assert min(W) > 0
+    assert np.array_equal(gw.cpu().numpy(), np.array(W))
     if var.startswith("fp32"):
         tot = t.forces_stats()["totals"]
         assert sum(W) == tot["wave_visits"] + tot["wave_leaves"]
@@ -126,9 +133,13 @@ def test_bounds_are_the_cost_zones(ctx, G):
     c1 = (1 + nm.cpu().numpy())[perm]
     assert np.array_equal(t.shard_bounds(G, nm, None).cpu().numpy(), cost_zones(c1, G))
     wk = torch.empty(n, dtype=torch.int64, device="cuda")
-    t.forces_range(0, n, None, None, None, None, wk)
+    gw = torch.empty((n + 63) // 64, dtype=torch.int64, device="cuda")
+    t.forces_range(0, n, None, None, None, None, wk, gw)
     cw = (1 + wk.cpu().numpy())[perm]
     assert np.array_equal(t.shard_bounds(G, wk).cpu().numpy(), cost_zones(cw, G))
+    bg = t.shard_bounds_groups(G, gw).cpu().numpy()
+    assert np.array_equal(bg, group_zones(gw.cpu().numpy(), n, G))
+    assert np.all((bg[:-1] % 64 == 0) | (bg[:-1] == n)) and bg[-1] == n
     eq = np.array([-(-j * n // G) for j in range(G + 1)], dtype=np.int64)
     assert np.array_equal(t.shard_bounds(G).cpu().numpy(), eq)
 
@@ -143,10 +154,13 @@ def test_bounds_over_many_chunks(ctx):
     np_ = rng.integers(0, 200, n)
     perm = t.export(with_mass=False)["perm"].long().cpu().numpy()
     cost = (1 + nm + np_)[perm]
+    gc = rng.integers(0, 100000, (n + 63) // 64)
     for G in (2, 8, 4096):
         b = t.shard_bounds(G, torch.tensor(nm, dtype=torch.int64, device="cuda"),
                            torch.tensor(np_, dtype=torch.int64, device="cuda")).cpu().numpy()
         assert np.array_equal(b, cost_zones(cost, G)), G
+        bg = t.shard_bounds_groups(G, torch.tensor(gc, dtype=torch.int64, device="cuda")).cpu().numpy()
+        assert np.array_equal(bg, group_zones(gc, n, G)), G
 
 
 def test_shards_cover_the_full_walk(ctx):
@@ -156,8 +170,9 @@ def test_shards_cover_the_full_walk(ctx):
         t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(0.5, 0.005, precision=prec)).upward()
         st = t.forces_stats()
         wk = torch.empty(n, dtype=torch.int64, device="cuda")
-        t.forces_range(0, n, None, None, None, None, wk)
-        for b in (t.shard_bounds(8, st["n_mono"], st["n_p2p"]), t.shard_bounds(8, wk)):
+        gw = torch.empty(n // 64, dtype=torch.int64, device="cuda")
+        t.forces_range(0, n, None, None, None, None, wk, gw)
+        for b in (t.shard_bounds(8, st["n_mono"], st["n_p2p"]), t.shard_bounds(8, wk), t.shard_bounds_groups(8, gw)):
             b = b.cpu().tolist()
             acc = nan_like(n, 3)
             for j in range(8):
@@ -179,6 +194,12 @@ def test_arguments_validated(ctx):
     for G in (0, -3, 65537):
         with pytest.raises(bh.BHError):
             t.shard_bounds(G)
+    gw = torch.zeros(5, dtype=torch.int64, device="cuda")
+    for G in (0, 65537):
+        with pytest.raises(bh.BHError):
+            t.shard_bounds_groups(G, gw)
+    with pytest.raises(bh.BHError):
+        t.shard_bounds_groups(4, None)
     acc = t.forces_range(300, 0)                # empty range at the end: nothing written
     assert torch.isnan(acc).all()
 
@@ -200,12 +221,16 @@ def test_tiny_trees(ctx, n):
             assert torch.equal(acc[perm[r]], st["acc"][perm[r]]), (prec, r)
         assert torch.equal(acc, st["acc"])
         wk = torch.empty(n, dtype=torch.int64, device="cuda")
-        t.forces_range(0, n, None, None, None, None, wk)
+        gw = torch.empty((n + 63) // 64, dtype=torch.int64, device="cuda")
+        t.forces_range(0, n, None, None, None, None, wk, gw)
         ps = perm.cpu().numpy()
         for G in (1, 3, 2 * n + 1):
             b = t.shard_bounds(G, wk).cpu().numpy()
             assert np.array_equal(b, cost_zones((1 + wk.cpu().numpy())[ps], G)), (prec, G)
-            acc2 = nan_like(n, 3)
-            for j in range(G):
-                t.forces_range(int(b[j]), int(b[j + 1] - b[j]), acc2)
-            assert torch.equal(acc2, st["acc"]), (prec, G)
+            bg = t.shard_bounds_groups(G, gw).cpu().numpy()
+            assert np.array_equal(bg, group_zones(gw.cpu().numpy(), n, G)), (prec, G)
+            for bb in (b, bg):
+                acc2 = nan_like(n, 3)
+                for j in range(G):
+                    t.forces_range(int(bb[j]), int(bb[j + 1] - bb[j]), acc2)
+                assert torch.equal(acc2, st["acc"]), (prec, G)
