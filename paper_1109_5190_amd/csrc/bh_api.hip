@@ -526,7 +526,10 @@ bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count,
     D.ngroups = (uint32_t)(g1 - g0);
     const bool stats = n_mono || n_p2p || work || group_work;
     if (stats) HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
-    HIPCHK(launch_walk(D, stats, pot != nullptr, acc, pot, n_mono, n_p2p, nullptr, ctx->stream, t->F.walk_waves,
+    // a part of the groups loses less to the launch's tail with one wavefront per workgroup
+    // (the whole tree keeps its own shape); the shape changes no result
+    const int waves = count == n ? t->F.walk_waves : 1;
+    HIPCHK(launch_walk(D, stats, pot != nullptr, acc, pot, n_mono, n_p2p, nullptr, ctx->stream, waves,
                        (uint32_t)first, (uint32_t)(first + count), work, group_work));
     return BH_OK;
 }
