@@ -22,3 +22,13 @@ def rel_max(a, ref):
 
 def u64(t):
     return t.cpu().numpy().view(np.uint64)
+
+
+def mix64(x):
+    """Interaction-set checksum mixer, vectorised: the SplitMix64 finalizer of x + golden gamma
+    (pinned against the generator's published outputs in tests/test_mix64_kat.py)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(x).astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))

@@ -8,7 +8,7 @@ import pytest
 
 import icgen
 import oracle
-from tests.gpu_helpers import dev
+from tests.gpu_helpers import dev, mix64
 
 pytestmark = pytest.mark.gpu
 
@@ -98,14 +98,6 @@ def chunks_for(G, nbytes):
     while c > 0 and layout(G, c)[4] > nbytes:
         c -= 1
     return c
-
-
-def mix64(x):
-    with np.errstate(over="ignore"):
-        z = x.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
 
 
 def decode(buf, n):
