@@ -1,0 +1,390 @@
+// FP32-mode force walk (see k_walk32).
+#include "bh_walk_common.h"
+
+namespace bh {
+
+// ------------------------------------------------------------- FP32 walk ---
+// Each wavefront re-expresses coordinates relative to its own FP64 reference
+// point g (its first body): FP32 differences then carry errors of order
+// u |d| + u |x - g| rather than u |x - origin|.
+//
+// Opening test in FP32: for theta > 0 the method accepts iff s^2 < theta^2 D^2,
+// i.e. iff E2 = |d|^2 + eps^2 exceeds S = s^2 / theta^2 + eps^2 (E2 is the
+// softened distance the monopole needs anyway, so the test costs one compare).
+// With rho an upper bound of |com - g|_inf + |x - g|_inf and u = 2^-24, the
+// computed E2 - S differs from the exact D^2 - s^2 / theta^2 by less than
+//   B = 16 u S + rho (8 u s / theta + 16 u^2 rho)
+// wherever the two could differ in sign (first-order terms about half of
+// these, the rho^2 term covers the case of a target within FP32 resolution of
+// a small cube).  Per child and wavefront the walk stages hi >= S + B and
+// lo <= S - B: E2 > hi accepts, E2 < lo opens, and the rare lanes in between
+// repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
+// into FP32 partial sums that are folded into Kahan-compensated totals after
+// at most 64 terms.
+template <bool STATS, bool POT, int W, bool QUAD, bool SOFT>
+__global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
+    __shared__ WaveLds32 lds_all[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    WaveLds32 &L = lds_all[wave];
+    const uint32_t gi = blockIdx.x * W + wave;
+    if (gi >= f.ngroups) return;
+    if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
+    const GroupDesc gd = f.groups[gi];
+    const uint32_t sid = uni(gd.seg);
+    const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 1 || sd.group || (sd.quad != 0) != QUAD || unsoftened(sd.eps) == SOFT) return;
+    const SegState &st = f.st[sid];
+    const uint32_t gstart = uni(gd.start);
+    const bool live = (uint32_t)lane < gd.count;
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
+    const double gx = f.spos[3 * (size_t)gstart], gy = f.spos[3 * (size_t)gstart + 1],
+                 gz = f.spos[3 * (size_t)gstart + 2];
+    const float tx = (float)__dsub_rn(f.spos[3 * (size_t)r], gx);
+    const float ty = (float)__dsub_rn(f.spos[3 * (size_t)r + 1], gy);
+    const float tz = (float)__dsub_rn(f.spos[3 * (size_t)r + 2], gz);
+    float rw = live ? fmaxf(fabsf(tx), fmaxf(fabsf(ty), fabsf(tz))) : 0.0f;
+    for (int o = 32; o > 0; o >>= 1) rw = fmaxf(rw, __shfl_xor(rw, o, 64));
+    rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
+    const double theta = sd.theta;
+    const float eps2 = (float)(sd.eps * sd.eps);
+    const float band2 = 16.0f * kU32 * kU32;   // 16 u^2
+    constexpr bool soft = SOFT;
+
+    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
+    float sx = 0.f, sy = 0.f, sz = 0.f, sp_ = 0.f;           // Kahan sums
+    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;            // Kahan compensations
+    uint32_t nmono = 0, np2p = 0, nvis = 0, nfb = 0;
+    uint32_t wvis = 0, went = 0, wacc = 0, wleaf = 0;         // wave-level counters (uniform)
+    uint64_t h = 0;
+    uint32_t work = 0;   // terms added to the partial sums since the last fold (wave-uniform)
+    uint32_t qn = 0;     // queued leaf particles (wave-uniform)
+    auto fold = [&]() {
+        kahan_add(sx, cx, ax); ax = 0.f;
+        kahan_add(sy, cy, ay); ay = 0.f;
+        kahan_add(sz, cz, az); az = 0.f;
+        if (POT) { kahan_add(sp_, cp, ap); ap = 0.f; }
+        work = 0;
+    };
+    auto pair = [&](float px, float py, float pz, float pm) {
+        const float dx = px - tx, dy = py - ty, dz = pz - tz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+        if (soft || r2 > 0.0f) {
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float mr = pm * ri;
+            const float w3 = mr * ri * ri;
+            ax = fmaf(w3, dx, ax);
+            ay = fmaf(w3, dy, ay);
+            az = fmaf(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    };
+    // queued leaf particles: load and convert lane-parallel, then one pass per particle
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
+    auto flush_leaves = [&]() {
+        if (qn == 0) return;
+        if (STATS) wwork += qn;
+        if (work + qn > kFlushWork) fold();
+        work += qn;
+        if (!SOFT) {
+            // without softening a pair can be far closer than the group's extent: each side
+            // is split as x - g = hi + lo (FP32 pair), so the difference of a close pair,
+            // (hi_j - hi_i) + (lo_j - lo_i), carries u |d| instead of u |x - g|
+            const float tlx = (float)(__dsub_rn(f.spos[3 * (size_t)r], gx) - (double)tx);
+            const float tly = (float)(__dsub_rn(f.spos[3 * (size_t)r + 1], gy) - (double)ty);
+            const float tlz = (float)(__dsub_rn(f.spos[3 * (size_t)r + 2], gz) - (double)tz);
+            for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+                const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    const size_t j = L.irank[k0 + lane];
+                    const double ex_ = __dsub_rn(f.spos[3 * j], gx), ey = __dsub_rn(f.spos[3 * j + 1], gy),
+                                 ez = __dsub_rn(f.spos[3 * j + 2], gz);
+                    const float hx = (float)ex_, hy = (float)ey, hz = (float)ez;
+                    L.pst[2 * lane] = make_float4(hx, hy, hz, (float)f.smass[j]);
+                    L.pst[2 * lane + 1] = make_float4((float)(ex_ - (double)hx), (float)(ey - (double)hy),
+                                                      (float)(ez - (double)hz), 0.0f);
+                }
+                wave_sync();
+                for (uint32_t k = 0; k < nb; ++k) {
+                    const uint32_t jq = uni(L.irank[k0 + k]);
+                    const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                    if (in_mask(m)) {
+                        const float4 ph = L.pst[2 * k], pl = L.pst[2 * k + 1];
+                        const float dx = (ph.x - tx) + (pl.x - tlx), dy = (ph.y - ty) + (pl.y - tly),
+                                    dz = (ph.z - tz) + (pl.z - tlz);
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (r2 > 0.0f) {
+                            const float ri = __builtin_amdgcn_rsqf(r2);
+                            const float mr = ph.w * ri;
+                            const float w3 = mr * ri * ri;
+                            ax = fmaf(w3, dx, ax);
+                            ay = fmaf(w3, dy, ay);
+                            az = fmaf(w3, dz, az);
+                            if (POT) ap -= mr;
+                        }
+                        if (STATS) {
+                            ++np2p;
+                            h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                        }
+                    }
+                }
+            }
+            qn = 0;
+            wave_sync();
+            return;
+        }
+        wave_sync();
+        if ((uint32_t)lane < qn) {
+            const size_t j = L.irank[lane];
+            L.pst[lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx), (float)__dsub_rn(f.spos[3 * j + 1], gy),
+                                      (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
+        }
+        wave_sync();
+        for (uint32_t k = 0; k < qn; ++k) {
+            const uint32_t jq = uni(L.irank[k]);
+            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
+            if (in_mask(m)) {
+                const float4 p = L.pst[k];
+                pair(p.x, p.y, p.z, p.w);
+                if (STATS) {
+                    ++np2p;
+                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    int sp = 0;
+    const uint64_t m0 = ballot(live);
+    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
+    wave_sync();
+    sp = 1;
+    while (sp > 0) {
+        --sp;
+        const uint4 e = L.stk[sp];
+        const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
+        const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+        wave_sync();
+        if ((uint32_t)lane < nch) {
+            const WRec32 &w = f.w32[link + lane];
+            const float qx = (float)__dsub_rn(w.cx, gx);
+            const float qy = (float)__dsub_rn(w.cy, gy);
+            const float qz = (float)__dsub_rn(w.cz, gz);
+            const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
+            const float B = fmaf(rho, fmaf(band2, rho, w.band1), w.band0);
+            L.sa[lane] = make_float4(qx, qy, qz, w.m);
+            L.sb[lane] = make_float2((w.Sp + B) * (1.0f + 4.0f * kU32), fmaxf(w.Sp - B, 0.0f) * (1.0f - 4.0f * kU32));
+            L.sl[lane] = make_uint2(w.link, w.cnt);
+            L.sc[lane] = make_uint2(w.gid, w.level);
+            if (QUAD) {
+                L.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
+                L.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
+            }
+        }
+        wave_sync();
+        if (work + nch > kFlushWork) fold();
+        work += nch;
+        if (STATS) { wvis += nch; ++went; }
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
+            const float4 qa = L.sa[c];
+            const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
+            const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+            uint64_t accm = ballot(E2 > L.sb[c].x) & emask;
+            uint64_t open = emask & ~accm;
+            if (open) {
+                const uint64_t ambm = ballot(!(E2 < L.sb[c].y)) & open;
+                if (ambm) {
+                    // within the FP32 rounding bound of the threshold: decide exactly in FP64
+                    bool ex = false;
+                    if (in_mask(ambm)) {
+                        const WRec32 &wc = f.w32[link + c];
+                        const double cm[3] = {wc.cx, wc.cy, wc.cz};
+                        const double *xp = f.spos + 3 * (size_t)r;
+                        const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
+                                     ez = __dsub_rn(cm[2], xp[2]);
+                        const double ED2 =
+                            __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
+                        ex = f.w32[link + c].r2 < __dmul_rn(__dmul_rn(theta, theta), ED2);
+                        if (STATS) ++nfb;
+                    }
+                    accm |= ballot(ex) & ambm;
+                    open = emask & ~accm;
+                }
+                if (open) {
+                    const uint2 ql = L.sl[c];
+                    const uint32_t qlink = uni(ql.x), qcnt = uni(ql.y);
+                    if (qcnt & kLeafBit) {
+                        const uint32_t np = qcnt & ~kLeafBit;
+                        if (STATS) ++wleaf;
+                        if (np <= 64u) {
+                            if (qn + np > 64u) flush_leaves();
+                            if ((uint32_t)lane < np) {
+                                L.irank[qn + lane] = qlink + lane;
+                                L.imask[qn + lane] = open;
+                            }
+                            qn += np;
+                        } else {
+                            // a leaf of more than 64 particles (coincident particles at the depth limit)
+                            flush_leaves();
+                            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                                if ((uint32_t)lane < nb) {
+                                    L.irank[lane] = qlink + b0 + lane;
+                                    L.imask[lane] = open;
+                                }
+                                qn = nb;
+                                flush_leaves();
+                            }
+                        }
+                    } else if (sp < kStackMax) {
+                        if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
+                        wave_sync();
+                        ++sp;
+                    } else if (lane == 0) {
+                        atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                    }
+                }
+            }
+            if (STATS) {
+                if (in_mask(emask)) ++nvis;
+                if (accm) ++wacc;
+            }
+            if (in_mask(accm)) {
+                // softened monopole, executed by the accepting lanes only
+                __asm__ volatile("");
+                const float ri = __builtin_amdgcn_rsqf(E2);
+                const float mr = qa.w * ri;
+                const float ri2 = ri * ri;
+                float w3 = mr * ri2;
+                if (QUAD) {
+                    // + G [5 A d / (2 s^7) - (3 S.d - tr S d) / s^5],  A = 3 d.S.d - s^2 tr S
+                    const float4 s0 = L.sq0[c], s1 = L.sq1[c];
+                    const float sdx = fmaf(s0.x, dx, fmaf(s0.w, dy, s1.x * dz));
+                    const float sdy = fmaf(s0.w, dx, fmaf(s0.y, dy, s1.y * dz));
+                    const float sdz = fmaf(s1.x, dx, fmaf(s1.y, dy, s0.z * dz));
+                    const float A = fmaf(3.0f, fmaf(dx, sdx, fmaf(dy, sdy, dz * sdz)), -E2 * s1.z);
+                    const float ri5 = ri2 * ri2 * ri;
+                    float qx = -ri5 * fmaf(3.0f, sdx, -s1.z * dx) + 2.5f * A * ri5 * ri2 * dx;
+                    float qy = -ri5 * fmaf(3.0f, sdy, -s1.z * dy) + 2.5f * A * ri5 * ri2 * dy;
+                    float qz = -ri5 * fmaf(3.0f, sdz, -s1.z * dz) + 2.5f * A * ri5 * ri2 * dz;
+                    float qp = -0.5f * A * ri5;
+                    // tr S > M s^2: the body is close to (or inside) the cube, the terms of the
+                    // expansion nearly cancel and FP32 loses them; those lanes take it in FP64
+                    const uint64_t hard = ballot(s1.z > qa.w * E2) & accm;
+                    if (hard) {
+                        if (in_mask(hard)) {
+                            const WRec32 &wc = f.w32[link + c];
+                            const double cm[3] = {wc.cx, wc.cy, wc.cz};
+                            const double *xp = f.spos + 3 * (size_t)r;
+                            const double *S = f.uQ + 6 * (size_t)(link + c);
+                            const double ex_ = cm[0] - xp[0], ey = cm[1] - xp[1], ez = cm[2] - xp[2];
+                            const double e2 = ((ex_ * ex_ + ey * ey) + ez * ez) + (double)sd.eps * sd.eps;
+                            const double tr = (S[0] + S[1]) + S[2];
+                            const double sx = fma(S[0], ex_, fma(S[3], ey, S[4] * ez));
+                            const double sy = fma(S[3], ex_, fma(S[1], ey, S[5] * ez));
+                            const double sz = fma(S[4], ex_, fma(S[5], ey, S[2] * ez));
+                            const double A64 = fma(3.0, fma(ex_, sx, fma(ey, sy, ez * sz)), -e2 * tr);
+                            const double rinv = 1.0 / sqrt(e2);
+                            const double r5 = rinv * rinv * rinv * rinv * rinv, r7 = r5 * rinv * rinv;
+                            qx = (float)(2.5 * A64 * r7 * ex_ - r5 * fma(3.0, sx, -tr * ex_));
+                            qy = (float)(2.5 * A64 * r7 * ey - r5 * fma(3.0, sy, -tr * ey));
+                            qz = (float)(2.5 * A64 * r7 * ez - r5 * fma(3.0, sz, -tr * ez));
+                            qp = (float)(-0.5 * A64 * r5);
+                        }
+                    }
+                    ax += qx;
+                    ay += qy;
+                    az += qz;
+                    if (POT) ap += qp;
+                }
+                ax = fmaf(w3, dx, ax);
+                ay = fmaf(w3, dy, ay);
+                az = fmaf(w3, dz, az);
+                if (POT) ap -= mr;
+                if (STATS) {
+                    ++nmono;
+                    h += mix64((uint64_t)(L.sc[c].x - st.nbase));
+                }
+            }
+        }
+    }
+    flush_leaves();
+    fold();
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
+    if (own) {
+        const uint32_t i = f.idx[r];
+        const size_t li = i - sd.start;
+        const double G = sd.G;
+        double *accb = seg_base(out.acc, sd.acc, sd, 3);
+        accb[3 * li] = G * ((double)sx - (double)cx);
+        accb[3 * li + 1] = G * ((double)sy - (double)cy);
+        accb[3 * li + 2] = G * ((double)sz - (double)cz);
+        if (POT) {
+            double *potb = seg_base(out.pot, sd.pot, sd, 1);
+            if (potb) potb[li] = G * ((double)sp_ - (double)cp);
+        }
+        if (STATS) {
+            if (out.n_mono) out.n_mono[i] = nmono;
+            if (out.n_p2p) out.n_p2p[i] = np2p;
+            if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
+        }
+    }
+    if (STATS) {
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0), fb = wave_sum_u(own ? nfb : 0);
+        if (lane == 0) {
+            atomicAdd(&f.stats[0], a);
+            atomicAdd(&f.stats[1], b);
+            atomicAdd(&f.stats[2], v);
+            atomicAdd(&f.stats[3], fb);
+            atomicAdd(&f.stats[4], (unsigned long long)wvis);
+            atomicAdd(&f.stats[5], (unsigned long long)went);
+            atomicAdd(&f.stats[6], (unsigned long long)wacc);
+            atomicAdd(&f.stats[7], (unsigned long long)wleaf);
+        }
+    }
+}
+
+
+template <bool STATS, bool POT, int W>
+static void launch_w32(const ForestDev &f, const WalkOut &o, hipStream_t s) {
+    const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
+    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, false>), g, b, 0, s, f, o);
+}
+
+template <bool POT>
+static void launch_w32_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
+    switch (W) {
+        case 1: launch_w32<false, POT, 1>(f, o, s); break;
+        case 2: launch_w32<false, POT, 2>(f, o, s); break;
+        case 8: launch_w32<false, POT, 8>(f, o, s); break;
+        default: launch_w32<false, POT, 4>(f, o, s); break;
+    }
+}
+
+void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
+    if (!(f.has32 & ~kVarGroup)) return;
+    if (stats) {   // the counting walks use one launch shape
+        if (pot) launch_w32<true, true, 4>(f, o, s);
+        else launch_w32<true, false, 4>(f, o, s);
+    } else if (pot) {
+        launch_w32_shape<true>(f, o, W, s);
+    } else {
+        launch_w32_shape<false>(f, o, W, s);
+    }
+}
+
+}  // namespace bh

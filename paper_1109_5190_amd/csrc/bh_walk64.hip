@@ -1,0 +1,239 @@
+// FP64-mode force walk (see k_walk64).
+#include "bh_walk_common.h"
+
+namespace bh {
+
+// ------------------------------------------------------------- FP64 walk ---
+
+
+template <bool STATS, bool POT, int W, bool QUAD>
+__global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
+    __shared__ WaveLds64<QUAD> lds_all[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    WaveLds64<QUAD> &L = lds_all[wave];
+    const uint32_t gi = blockIdx.x * W + wave;
+    if (gi >= f.ngroups) return;
+    if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
+    const GroupDesc gd = f.groups[gi];
+    const uint32_t sid = uni(gd.seg);
+    const SegDesc &sd = f.seg[sid];
+    if (sd.precision != 0 || sd.group || (sd.quad != 0) != QUAD) return;
+    const SegState &st = f.st[sid];
+    const uint32_t gstart = uni(gd.start);
+    const bool live = (uint32_t)lane < gd.count;
+    const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
+    const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
+    const double theta2 = __dmul_rn(sd.theta, sd.theta);
+    const double eps2 = __dmul_rn(sd.eps, sd.eps);
+    const bool soft = eps2 > 0.0;
+
+    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
+    uint32_t nmono = 0, np2p = 0, nvis = 0;
+    uint64_t h = 0;
+    uint32_t qn = 0;
+    auto pair = [&](double px, double py, double pz, double pm) {
+        const double dx = px - tx, dy = py - ty, dz = pz - tz;
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+        if (soft || r2 > 0.0) {
+            const double ri = rsqrt64(r2);
+            const double mr = pm * ri;
+            const double w3 = mr * ri * ri;
+            ax = fma(w3, dx, ax);
+            ay = fma(w3, dy, ay);
+            az = fma(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    };
+    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
+    auto flush_leaves = [&]() {
+        if (qn == 0) return;
+        if (STATS) wwork += qn;
+        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+            wave_sync();
+            if ((uint32_t)lane < nb) {
+                const size_t j = L.irank[k0 + lane];
+                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+            }
+            wave_sync();
+            for (uint32_t k = 0; k < nb; ++k) {
+                const uint32_t jq = uni(L.irank[k0 + k]);
+                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                if (in_mask(m)) {
+                    const double4 p = L.pst[k];
+                    pair(p.x, p.y, p.z, p.w);
+                    if (STATS) {
+                        ++np2p;
+                        h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
+                    }
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    int sp = 0;
+    const uint64_t m0 = ballot(live);
+    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
+    wave_sync();
+    sp = 1;
+    while (sp > 0) {
+        --sp;
+        const uint4 e = L.stk[sp];
+        const uint32_t link = uni(e.x), nch = uni(e.y);
+        if (STATS) wwork += nch;
+        const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+        wave_sync();
+        if ((uint32_t)lane < nch) {
+            const WRec64 &w = f.w64[link + lane];
+            L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
+            L.sS[lane] = w.S;
+            L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
+            if (QUAD)
+                for (int k = 0; k < 6; ++k) L.sq[6 * lane + k] = f.q64[6 * (size_t)(link + lane) + k];
+        }
+        wave_sync();
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (c >= nch) break;
+            const double4 qa = L.sa[c];
+            const double S = L.sS[c];
+            const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
+            const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            const uint64_t accm = ballot(S < __dmul_rn(theta2, D2)) & emask;
+            if (STATS && in_mask(emask)) ++nvis;
+            const uint64_t open = emask & ~accm;
+            if (open) {
+                const uint4 qb = L.sb[c];
+                const uint32_t qlink = uni(qb.x), qcnt = uni(qb.y);
+                if (qcnt & kLeafBit) {
+                    const uint32_t np = qcnt & ~kLeafBit;
+                    if (np <= 64u) {
+                        if (qn + np > 64u) flush_leaves();
+                        if ((uint32_t)lane < np) {
+                            L.irank[qn + lane] = qlink + lane;
+                            L.imask[qn + lane] = open;
+                        }
+                        qn += np;
+                    } else {
+                        flush_leaves();
+                        for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                            const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                            if ((uint32_t)lane < nb) {
+                                L.irank[lane] = qlink + b0 + lane;
+                                L.imask[lane] = open;
+                            }
+                            qn = nb;
+                            flush_leaves();
+                        }
+                    }
+                } else if (sp < kStackMax) {
+                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
+                    wave_sync();
+                    ++sp;
+                } else if (lane == 0) {
+                    atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                }
+            }
+            if (in_mask(accm)) {
+                // softened monopole, executed by the accepting lanes only
+                __asm__ volatile("");
+                const double E2 = D2 + eps2;
+                const double ri = rsqrt64(E2);
+                const double mr = qa.w * ri;
+                const double ri2 = ri * ri;
+                double w3 = mr * ri2;
+                if (QUAD) {
+                    const double *q = &L.sq[6 * c];
+                    const double sdx = fma(q[0], dx, fma(q[3], dy, q[4] * dz));
+                    const double sdy = fma(q[3], dx, fma(q[1], dy, q[5] * dz));
+                    const double sdz = fma(q[4], dx, fma(q[5], dy, q[2] * dz));
+                    const double tr = (q[0] + q[1]) + q[2];
+                    const double A = fma(3.0, fma(dx, sdx, fma(dy, sdy, dz * sdz)), -E2 * tr);
+                    const double ri5 = ri2 * ri2 * ri;
+                    w3 = fma(2.5 * A, ri5 * ri2, w3);
+                    ax = fma(-ri5, fma(3.0, sdx, -tr * dx), ax);
+                    ay = fma(-ri5, fma(3.0, sdy, -tr * dy), ay);
+                    az = fma(-ri5, fma(3.0, sdz, -tr * dz), az);
+                    if (POT) ap -= 0.5 * A * ri5;
+                }
+                ax = fma(w3, dx, ax);
+                ay = fma(w3, dy, ay);
+                az = fma(w3, dz, az);
+                if (POT) ap -= mr;
+                if (STATS) {
+                    ++nmono;
+                    h += mix64((uint64_t)(L.sb[c].z - st.nbase));
+                }
+            }
+        }
+    }
+    flush_leaves();
+    const bool own = live && r >= out.wlo && r < out.whi;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
+    if (own) {
+        const uint32_t i = f.idx[r];
+        const size_t li = i - sd.start;
+        const double G = sd.G;
+        double *accb = seg_base(out.acc, sd.acc, sd, 3);
+        accb[3 * li] = G * ax;
+        accb[3 * li + 1] = G * ay;
+        accb[3 * li + 2] = G * az;
+        if (POT) {
+            double *potb = seg_base(out.pot, sd.pot, sd, 1);
+            if (potb) potb[li] = G * ap;
+        }
+        if (STATS) {
+            if (out.n_mono) out.n_mono[i] = nmono;
+            if (out.n_p2p) out.n_p2p[i] = np2p;
+            if (out.hash) out.hash[i] = h;
+            if (out.work) {   // the group's wavefront work, spread evenly over its bodies
+                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
+            }
+        }
+    }
+    if (STATS) {
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long v = wave_sum_u(own ? nvis : 0);
+        if (lane == 0) {
+            atomicAdd(&f.stats[0], a);
+            atomicAdd(&f.stats[1], b);
+            atomicAdd(&f.stats[2], v);
+        }
+    }
+}
+
+
+template <bool STATS, bool POT, int W>
+static void launch_w64(const ForestDev &f, const WalkOut &o, hipStream_t s) {
+    const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
+    if (f.has64 & (var_bit(false, false) | var_bit(false, true)))
+        hipLaunchKernelGGL((k_walk64<STATS, POT, W, false>), g, b, 0, s, f, o);
+    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true>), g, b, 0, s, f, o);
+}
+
+template <bool POT>
+static void launch_w64_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
+    switch (W) {
+        case 1: launch_w64<false, POT, 1>(f, o, s); break;
+        case 2: launch_w64<false, POT, 2>(f, o, s); break;
+        case 8: launch_w64<false, POT, 8>(f, o, s); break;
+        default: launch_w64<false, POT, 4>(f, o, s); break;
+    }
+}
+
+void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
+    if (!(f.has64 & ~kVarGroup)) return;
+    if (stats) {   // the counting walks use one launch shape
+        if (pot) launch_w64<true, true, 4>(f, o, s);
+        else launch_w64<true, false, 4>(f, o, s);
+    } else if (pot) {
+        launch_w64_shape<true>(f, o, W, s);
+    } else {
+        launch_w64_shape<false>(f, o, W, s);
+    }
+}
+
+}  // namespace bh
