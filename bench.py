@@ -31,24 +31,42 @@ FP32_PEAK = 157.3e12     # MI355X vector FP32 (packed issue)
 FP64_PEAK = 78.6e12      # MI355X vector FP64
 FLOPS_PER_INTERACTION = 20
 TRAFFIC_SUMMARY = ROOT / "profiles" / "hbm_traffic_plummer_1M.md"
-WALK_SOURCE = ROOT / "paper_1109_5190_amd" / "csrc" / "bh_walk.hip"
+VALU_SUMMARY = ROOT / "profiles" / "walk_instruction_mix_plummer_1M.md"
+WALK_SOURCES = [ROOT / "paper_1109_5190_amd" / "csrc" / f for f in ("bh_walk32.hip", "bh_walk_common.h", "bh_common.h")]
 
 
-def walk_traffic(n):
-    """HBM bytes per FP32 walk launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, calibrated on a copy kernel), or None when the summary was taken on
-    another workload size or on a different walk source."""
+def walk_source_sha():
     import hashlib
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        h.update(f.read_bytes())
+    return h.hexdigest()
+
+
+def profile_figure(path, tag, n):
+    """A per-launch figure of the FP32 walk from a committed counter summary (its line
+    `<tag>: kernel=k_walk32 n=<n> value=<v> source-sha256=<sha>`), or None when the
+    summary was taken on another workload size or on a different walk source."""
     import re
     try:
-        text = TRAFFIC_SUMMARY.read_text()
-        sha = hashlib.sha256(WALK_SOURCE.read_bytes()).hexdigest()
+        text = path.read_text()
+        sha = walk_source_sha()
     except OSError:
         return None
-    m = re.search(r"bench-traffic: kernel=k_walk32 n=(\d+) bytes=(\d+) source-sha256=([0-9a-f]+)", text)
+    m = re.search(tag + r": kernel=k_walk32 n=(\d+) value=(\d+) source-sha256=([0-9a-f]+)", text)
     if not m or int(m.group(1)) != n or m.group(3) != sha:
         return None
     return int(m.group(2))
+
+
+def walk_traffic(n):
+    """HBM bytes per FP32 walk launch (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated)."""
+    return profile_figure(TRAFFIC_SUMMARY, "bench-traffic", n)
+
+
+def walk_valu(n):
+    """VALU instructions (SQ_INSTS_VALU, wavefront instructions) per FP32 walk launch."""
+    return profile_figure(VALU_SUMMARY, "bench-valu", n)
 
 
 def parse():
@@ -67,9 +85,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--shards", type=int, default=8, help="targets split for one GPU's share (0: skip)")
     ap.add_argument("--precisions", default="fp32,fp64")
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-precision", default="fp32")
+    ap.add_argument("--serve-precisions", default="fp32,fp64",
+                    help="serving runs at --serve-rate; the first is repeated near its measured capacity")
+    ap.add_argument("--no-leaf16", action="store_true", help="skip the leaf_cap 16 leg")
     ap.add_argument("--workload", choices=("plummer1m", "sweep", "batch"), default="plummer1m",
                     help="plummer1m: the headline line; sweep: the two-sphere and cube systems of 2^22 over "
                          "theta; batch: 512 simulations as one forest (each prints its own JSON line)")
@@ -234,63 +254,53 @@ def batch(a, bh, torch):
                                       "sample": "256 targets on each of 8 instances stratified by N, initial positions"}}
 
 
-def one_gpu_share(a, tree, st, stream, torch, ms_walk):
+def one_gpu_share(a, tree, stream, torch, ms_walk, acc_full):
     """The walk of one GPU's share when the targets are split G ways (each GPU holding the whole
-    tree): ranges from the cost zones of a previous counting walk (interaction counts `st`, each
-    group's wavefront work spread over its bodies, or the same work per group with ranges on group
-    boundaries) and from equal counts, each range walked alone on the whole GPU.
-    The ranges together reproduce the full walk's bits."""
+    tree): ranges on 64-body group boundaries balanced by each group's wavefront work from a
+    counting walk, each range walked alone on the whole GPU.  The ranges together reproduce the
+    full walk's bits."""
     G = a.shards
-    out = {"G": G}
+    out = {"G": G, "split": "group zones (wavefront work of each 64-body walk group)"}
+    acc = torch.empty_like(acc_full)
+    gwork = torch.empty((tree.n + 63) // 64, dtype=torch.int64, device=acc.device)
+    tree.forces_range(0, tree.n, acc, None, None, None, None, gwork)   # counting walk: wavefront work
+    torch.cuda.synchronize()
     b0, b1 = _events(torch)
     b0.record(stream)
     for _ in range(a.walk_reps):
-        bounds = tree.shard_bounds(G, st["n_mono"], st["n_p2p"])
+        bounds = tree.shard_bounds_groups(G, gwork)
     b1.record(stream)
     torch.cuda.synchronize()
     out["bounds_ms"] = b0.elapsed_time(b1) / a.walk_reps
-    acc = torch.empty_like(st["acc"])
-    work = torch.empty(tree.n, dtype=torch.int64, device=acc.device)
-    gwork = torch.empty((tree.n + 63) // 64, dtype=torch.int64, device=acc.device)
-    tree.forces_range(0, tree.n, acc, None, None, None, work, gwork)   # counting walk: wavefront work
-    torch.cuda.synchronize()
-    b0.record(stream)
-    for _ in range(a.walk_reps):
-        gbounds = tree.shard_bounds_groups(G, gwork)
-    b1.record(stream)
-    torch.cuda.synchronize()
-    out["bounds_groups_ms"] = b0.elapsed_time(b1) / a.walk_reps
-    splits = (("cost_zones", bounds), ("work_zones", tree.shard_bounds(G, work)), ("group_zones", gbounds),
-              ("equal_counts", tree.shard_bounds(G)))
-    for name, bl in ((k, b.cpu().tolist()) for k, b in splits):
-        ms = []
-        for j in range(G):
+    bl = bounds.cpu().tolist()
+    ms = []
+    for j in range(G):
+        tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(a.walk_reps):
             tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
-            e0, e1 = _events(torch)
-            e0.record(stream)
-            for _ in range(a.walk_reps):
-                tree.forces_range(bl[j], bl[j + 1] - bl[j], acc)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1) / a.walk_reps)
-        out[name] = {"ms": ms, "max_ms": max(ms), "sum_ms": sum(ms), "imbalance": max(ms) * G / sum(ms),
-                     "full_walk_over_G_vs_max": ms_walk / G / max(ms),
-                     "bitwise_equal_to_walk": bool(torch.equal(acc, st["acc"]))}
-    print(f"# one GPU's share of {G} (max ms, imbalance): " + ", ".join(
-        f"{k} {out[k]['max_ms']:.3f} {out[k]['imbalance']:.3f}" for k, _ in splits), file=sys.stderr, flush=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1) / a.walk_reps)
+    out.update(ms=ms, max_ms=max(ms), sum_ms=sum(ms), imbalance=max(ms) * G / sum(ms),
+               full_walk_over_G_vs_max=ms_walk / G / max(ms), bitwise_equal_to_walk=bool(torch.equal(acc, acc_full)))
+    print(f"# one GPU's share of {G}: slowest range {out['max_ms']:.3f} ms, imbalance {out['imbalance']:.3f}",
+          file=sys.stderr, flush=True)
     return out
 
 
-def serve(a, bh, ctx, torch):
-    """Serving leg: Poisson arrivals of simulation requests through the continuous-batching server."""
+def serve(a, bh, ctx, torch, precision, rate, nreq):
+    """Serving run: Poisson arrivals of simulation requests through the continuous-batching
+    server; latency is done - submit per request."""
     import numpy as np
 
     import icgen
-    reqs = icgen.request_stream(a.serve_requests, a.serve_rate, master_seed=7)
+    reqs = icgen.request_stream(nreq, rate, master_seed=7)
     free = torch.cuda.mem_get_info()[0]
     arena = int(min(48 << 30, free * 0.6))
     sv = bh.Server(ctx, arena, max_slots=64, max_resident=1 << 24)
-    p = bh.params(0.5, 0.01, 1.0, 1, a.serve_precision)
+    p = bh.params(0.5, 0.01, 1.0, 1, precision)
     t0 = sv.now()
     ids = []
     for r in reqs:
@@ -309,16 +319,77 @@ def serve(a, bh, ctx, torch):
     ok = [d for d in done if d["state"] == "done"]
     lat = np.array([d["t_done"] - d["t_submit"] for d in ok])
     wait = np.array([d["t_admit"] - d["t_submit"] for d in ok])
+    service = np.array([d["t_done"] - d["t_admit"] for d in ok])
     work = sum(r["n"] * r["steps"] for r, d in zip(reqs, done) if d["state"] == "done")
     span = max(d["t_done"] for d in ok) - min(d["t_submit"] for d in ok)
-    offered = a.serve_rate * float(np.mean([r["n"] * r["steps"] for r in reqs]))
-    return {"requests": len(reqs), "completed": len(ok), "rate_req_per_s": a.serve_rate,
-            "precision": a.serve_precision, "p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99)), "mean_queue_wait_s": float(wait.mean()),
-            "throughput_particle_steps_per_s": work / span, "offered_particle_steps_per_s": offered,
-            "makespan_s": span, "arena_bytes": arena, "max_slots": 64, "max_resident": 1 << 24,
-            "workload": "Poisson arrivals, N log-uniform in [4096, 4194304], steps uniform 1..100, "
-                        "Plummer or cube 50/50, theta=0.5, eps=0.01, dt=1e-3, seed 7"}
+    offered = rate * float(np.mean([r["n"] * r["steps"] for r in reqs]))
+    out = {"requests": len(reqs), "completed": len(ok), "rate_req_per_s": rate, "precision": precision,
+           "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+           "max_latency_s": float(lat.max()), "mean_queue_wait_s": float(wait.mean()),
+           "mean_service_s": float(service.mean()),
+           "throughput_particle_steps_per_s": work / span, "offered_particle_steps_per_s": offered,
+           "makespan_s": span, "arena_bytes": arena, "max_slots": 64, "max_resident": 1 << 24,
+           "workload": "Poisson arrivals, N log-uniform in [4096, 4194304], steps uniform 1..100, "
+                       "Plummer or cube 50/50, theta=0.5, eps=0.01, dt=1e-3, seed 7"}
+    print(f"# serving {precision} at {rate:.1f} req/s, R={len(reqs)}: p50 {out['p50_latency_s']:.3f}s "
+          f"p99 {out['p99_latency_s']:.3f}s, {out['throughput_particle_steps_per_s']:.3e} particle-steps/s",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def leaf16(a, bh, torch, stream, pos0, vel0, mass, s):
+    """The headline configuration with leaves of up to 16 particles (FP32): step and walk
+    times, interactions per particle and the error against the oracle on sampled targets."""
+    import numpy as np
+
+    import oracle
+    p = bh.params(a.theta, a.eps, 1.0, 16, "fp32")
+    sim = bh.Sim(ctx_of(bh, torch), pos0.clone(), vel0.clone(), mass, p)
+    sim.step(1, a.dt)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    steps = max(2, min(a.steps, 5))
+    e0.record(stream)
+    sim.step(steps, a.dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    tree = bh.Tree(sim.ctx, pos0, mass, p).upward()
+    st = tree.forces_stats()
+    w0, w1 = _events(torch)
+    w0.record(stream)
+    for _ in range(a.walk_reps):
+        tree.forces()
+    w1.record(stream)
+    torch.cuda.synchronize()
+    ms_walk = w0.elapsed_time(w1) / a.walk_reps
+    tot = st["totals"]
+    inter = tot["n_mono"] + tot["n_p2p"]
+    rng = np.random.default_rng(1)
+    ns = min(16384, a.n)
+    tg = np.sort(rng.choice(a.n, ns, replace=False)).astype(np.int64)
+    ref = oracle.Tree(s.pos, s.mass, 16).walk(a.theta, a.eps, 1.0, tg, nthreads=len(os.sched_getaffinity(0)))
+    rms, mx = _errors(st["acc"].cpu().numpy()[tg], ref["acc"])
+    sets_equal = bool(np.array_equal(st["n_mono"].cpu().numpy()[tg], ref["n_mono"]) and
+                      np.array_equal(st["hash"].cpu().numpy().view(np.uint64)[tg], ref["hash"]))
+    out = {"leaf_cap": 16, "precision": "fp32", "ms_per_step": ms_step, "value": a.n / (ms_step * 1e-3) / 1e6,
+           "walk_ms": ms_walk, "interactions_per_particle": inter / a.n,
+           "walk_tflops": FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / 1e12,
+           "force_error_vs_oracle": {"rms_rel": rms, "max_rel": mx, "interaction_sets_equal": sets_equal,
+                                     "sample": f"{ns} random targets at the initial positions"}}
+    print(f"# leaf_cap 16: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, {inter / a.n:.1f} interactions/particle, "
+          f"rms {rms:.2e}", file=sys.stderr, flush=True)
+    return out
+
+
+_CTX = None
+
+
+def ctx_of(bh, torch):
+    global _CTX
+    if _CTX is None:
+        _CTX = bh.Context(0)
+    return _CTX
 
 
 def main():
@@ -346,7 +417,7 @@ def main():
     pos0 = torch.tensor(s.pos, device=dev)
     vel0 = torch.tensor(s.vel, device=dev)
     mass = torch.tensor(s.mass, device=dev)
-    ctx = bh.Context(0)
+    ctx = ctx_of(bh, torch)
     stream = torch.cuda.current_stream(dev)
 
     results = {}
@@ -410,7 +481,7 @@ def main():
         del buf
         st = tree.forces_stats()
         torch.cuda.synchronize()
-        shards = one_gpu_share(a, tree, st, stream, torch, ms_walk) if a.shards > 1 else None
+        shards = one_gpu_share(a, tree, stream, torch, ms_walk, st["acc"]) if a.shards > 1 else None
         tot = st["totals"]
         inter = int(tot["n_mono"] + tot["n_p2p"])
         results[prec] = dict(ms_per_step=ms_step, ms_walk=ms_walk, ms_build_upward=ms_build,
@@ -452,7 +523,12 @@ def main():
                       "fp64_fallback_tests": r["fallbacks"], "opening_tests": r["visits"],
                       "wave_visits": r["wave_visits"], "wave_entries": r["wave_entries"],
                       "wave_accepts": r["wave_accepts"], "wave_leaves": r["wave_leaves"],
-                      "lane_utilisation": r["interactions"] / max(1, 64 * r["wave_visits"])},
+                      "lane_utilisation": r["interactions"] / max(1, 64 * r["wave_visits"]),
+                      "valu_insts_per_launch": walk_valu(a.n) if head == "fp32" else None,
+                      "valu_lane_slots_per_interaction": (64 * walk_valu(a.n) / r["interactions"]
+                                                          if head == "fp32" and walk_valu(a.n) else None),
+                      "valu_source": "SQ_INSTS_VALU of the committed counter summary, when taken on this walk "
+                                     "source (else null)"},
         "build_upward_ms": r["ms_build_upward"],
     }
     if r.get("lists"):
@@ -474,10 +550,20 @@ def main():
         if rr.get("shards"):
             out[prec]["one_gpu_share"] = rr["shards"]
 
+    if not a.no_leaf16:
+        out["leaf_cap_16"] = leaf16(a, bh, torch, stream, pos0, vel0, mass, s)
+
     if a.serve_requests > 0:
-        out["serving"] = serve(a, bh, ctx, torch)
-        print(f"# serving: p50 {out['serving']['p50_latency_s']:.3f}s p99 {out['serving']['p99_latency_s']:.3f}s",
-              file=sys.stderr, flush=True)
+        runs = {}
+        precs = [x for x in a.serve_precisions.split(",") if x]
+        for prec in precs:
+            runs[prec] = serve(a, bh, ctx, torch, prec, a.serve_rate, a.serve_requests)
+        # near capacity: the first precision again at 90 % of the request rate its overloaded run sustained
+        first = runs[precs[0]]
+        mean_work = first["offered_particle_steps_per_s"] / first["rate_req_per_s"]
+        lam = 0.9 * first["throughput_particle_steps_per_s"] / mean_work
+        runs[precs[0] + "_near_capacity"] = serve(a, bh, ctx, torch, precs[0], lam, a.serve_requests)
+        out["serving"] = runs
 
     if not a.no_cpu:
         import oracle

@@ -31,6 +31,12 @@
  *    returns once its work is enqueued.  Outputs are valid after the stream
  *    is synchronised (bh_ctx_sync).  Calls marked SYNC synchronise the stream
  *    themselves.
+ *  - Device faults: kernels record faults (walk stack overflow, an
+ *    inconsistent tree, a non-finite position or mass) in a fault word of the
+ *    tree, simulation or forest they run for.  The next SYNC call on that
+ *    object, or bh_ctx_sync, reports them (BH_E_OVERFLOW or BH_E_DEVICE) and
+ *    clears them, so later calls start clean.  A tree found inconsistent is
+ *    not walked (its outputs keep their contents) until it is rebuilt.
  *  - Layouts: positions, velocities and accelerations are row-major (n, 3)
  *    FP64 arrays in device memory in the caller's particle order; masses are
  *    (n,) FP64.  Results come back in the caller's order.
@@ -49,7 +55,7 @@ typedef enum {
     BH_OK = 0,
     BH_E_INVAL = 1,      /* bad argument (null pointer, n < 1, theta < 0, eps < 0, leaf_cap not in [1,64], non-finite) */
     BH_E_NOMEM = 2,      /* workspace / arena too small, or a request that can never fit */
-    BH_E_DEVICE = 3,     /* HIP error, or a device-side fault flag (non-finite state) */
+    BH_E_DEVICE = 3,     /* HIP error, or a device-side fault flag (non-finite position or mass) */
     BH_E_BUSY = 4,       /* request not finished yet */
     BH_E_NOTFOUND = 5,   /* unknown request id */
     BH_E_OVERFLOW = 6,   /* walk stack overflow (cannot happen for depth <= 21; reported if it does) */
@@ -119,6 +125,7 @@ typedef struct {
     /* wavefront-level diagnostics (FP32 mode; 0 in FP64 mode): cube visits, popped
      * stack entries, visits where at least one lane accepted, opened leaves */
     uint64_t wave_visits, wave_entries, wave_accepts, wave_leaves;
+    double t_ms;          /* the walk's duration on the stream (HIP events around its launch) */
 } bh_stats;
 
 typedef struct bh_ctx bh_ctx;
@@ -133,7 +140,8 @@ typedef struct bh_server bh_server;
  * NULL = the null stream).  The stream is not owned. */
 bh_status bh_ctx_create(int device, void *hip_stream, bh_ctx **out);
 bh_status bh_ctx_destroy(bh_ctx *ctx);
-/* SYNC: waits for the stream and reports a pending device-side fault flag. */
+/* SYNC: waits for the stream, then reports (and clears) the fault flags of
+ * the context's live trees, simulations and forests, the first found. */
 bh_status bh_ctx_sync(bh_ctx *ctx);
 const char *bh_last_error(void);
 /* Library version string, e.g. "bh-mi355x 0.1". */
@@ -283,9 +291,16 @@ bh_status bh_tree_info(bh_ctx *ctx, bh_tree *tree, int64_t *n_nodes, double lo[3
  * perm (n, perm[r] = original index of rank r), and per node in depth-first
  * preorder with children in ascending octant order: level, first rank, count,
  * parent (-1 for the root), mass M and centre of mass com (n_nodes x 3).
- * Node arrays must hold bh_tree_info's n_nodes entries. */
+ * Node arrays must hold bh_tree_info's n_nodes entries.
+ * n_nodes (host, nullable) receives the node count.  isect_hash (device, n,
+ * caller's order, nullable) receives each body's interaction-set checksum as
+ * bh_forces_stats defines it (section 3: each body's list of accepted cubes
+ * and partner bodies), from a counting walk that writes nothing else.
+ * SYNC when n_nodes or isect_hash is given, else asynchronous.  M, com and
+ * isect_hash need bh_upward first (BH_E_INVAL otherwise). */
 bh_status bh_tree_export(bh_ctx *ctx, bh_tree *tree, uint64_t *keys, uint32_t *perm, int32_t *level,
-                         uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com);
+                         uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com,
+                         int64_t *n_nodes, uint64_t *isect_hash);
 
 bh_status bh_tree_free(bh_ctx *ctx, bh_tree *tree);
 
@@ -337,13 +352,21 @@ bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *f);
 
 /* ----------------------------------------------------- initial conditions --- */
 
+/* Bytes of device workspace bh_ic_generate needs (independent of n: the
+ * generator's per-block partial sums and its fault word). */
+size_t bh_ic_workspace_bytes(void);
+
 /* Device-side generation of the same inputs as the host generator: Philox4x32-10
  * keyed by seed, counter (i_lo, i_hi, call, tag).  kind 0: Plummer sphere by
  * Aarseth-Henon-Wielen with scale radius a, total mass M, mass-fraction cut
  * 0.999, shifted to its centre-of-mass frame; kind 1: uniform cube [-a, a]^3,
- * masses uniform in [0.5, 1.5] M / n, at rest.  pos, vel (n x 3), mass (n). */
+ * masses uniform in [0.5, 1.5] M / n, at rest.  pos, vel (n x 3), mass (n):
+ * device outputs.  ws: caller-owned device workspace, 256-byte aligned, of
+ * ws_bytes >= bh_ic_workspace_bytes() (BH_E_NOMEM otherwise).  SYNC: returns
+ * BH_E_DEVICE if a velocity draw found no acceptance (the Plummer sampler
+ * gives up after 401 rejection rounds; never seen in practice). */
 bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M,
-                         double *pos, double *vel, double *mass);
+                         double *pos, double *vel, double *mass, void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- serving --- */
 

@@ -50,7 +50,7 @@ def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False,
 class Stats(C.Structure):
     _fields_ = [("n_mono", C.c_uint64), ("n_p2p", C.c_uint64), ("n_visits", C.c_uint64),
                 ("n_fallback", C.c_uint64), ("wave_visits", C.c_uint64), ("wave_entries", C.c_uint64),
-                ("wave_accepts", C.c_uint64), ("wave_leaves", C.c_uint64)]
+                ("wave_accepts", C.c_uint64), ("wave_leaves", C.c_uint64), ("t_ms", C.c_double)]
 
 
 class Request(C.Structure):
@@ -82,7 +82,7 @@ _SIGS = {
     "bh_shard_bounds": ([_VP, _VP, _VP, _VP, C.c_int32, _VP], C.c_int),
     "bh_shard_bounds_groups": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int),
     "bh_tree_info": ([_VP, _VP, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
-    "bh_tree_export": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "bh_tree_export": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_int64), _VP], C.c_int),
     "bh_tree_free": ([_VP, _VP], C.c_int),
     "bh_sim_workspace_bytes": ([C.c_int64, C.POINTER(Params)], C.c_size_t),
     "bh_sim_create": ([_VP, C.c_int64, _VP, _VP, _VP, _VP, C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)],
@@ -99,7 +99,9 @@ _SIGS = {
     "bh_forest_autotune": ([_VP, _VP, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
     "bh_forest_energy": ([_VP, _VP, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_destroy": ([_VP, _VP], C.c_int),
-    "bh_ic_generate": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP], C.c_int),
+    "bh_ic_workspace_bytes": ([], C.c_size_t),
+    "bh_ic_generate": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP, _VP,
+                        C.c_size_t], C.c_int),
     "bh_server_create": ([_VP, _VP, C.c_size_t, C.c_int32, C.c_int64, C.POINTER(_VP)], C.c_int),
     "bh_server_submit": ([_VP, C.POINTER(Request), C.POINTER(C.c_uint64)], C.c_int),
     "bh_server_poll": ([_VP, C.c_uint64, C.POINTER(Result)], C.c_int),
@@ -273,8 +275,9 @@ class Tree:
         st = Stats()
         _check(lib().bh_forces_stats(self.ctx.h, self.h, _ptr(acc), _ptr(ph), _ptr(nm), _ptr(np_), _ptr(hs),
                                      C.byref(st)))
-        return dict(acc=acc, pot=ph, n_mono=nm, n_p2p=np_, hash=hs,
-                    totals={k: int(getattr(st, k)) for k, _ in Stats._fields_})
+        totals = {k: int(getattr(st, k)) for k, _ in Stats._fields_ if k != "t_ms"}
+        totals["t_ms"] = float(st.t_ms)
+        return dict(acc=acc, pot=ph, n_mono=nm, n_p2p=np_, hash=hs, totals=totals)
 
     def forces_range(self, first, count, acc=None, pot=None, n_mono=None, n_p2p=None, work=None, group_work=None):
         """bh_forces_range: rows of the bodies of sorted ranks [first, first + count) in acc (and pot,
@@ -308,7 +311,9 @@ class Tree:
         _check(lib().bh_tree_info(self.ctx.h, self.h, C.byref(nn), lo, C.byref(k)))
         return int(nn.value), [lo[0], lo[1], lo[2]], int(k.value)
 
-    def export(self, with_mass=True):
+    def export(self, with_mass=True, with_hash=False):
+        """bh_tree_export: keys, perm and the node arrays (device tensors), the node count,
+        and with_hash the per-body interaction-set checksums (needs upward())."""
         torch = _torch()
         nn, lo, k = self.info()
         dev = self.pos.device
@@ -321,10 +326,14 @@ class Tree:
             parent=torch.empty(nn, dtype=torch.int32, device=dev),
             M=torch.empty(nn, dtype=torch.float64, device=dev) if with_mass else None,
             com=torch.empty((nn, 3), dtype=torch.float64, device=dev) if with_mass else None,
+            isect_hash=torch.empty(self.n, dtype=torch.int64, device=dev) if with_hash else None,
         )
+        nno = C.c_int64(-1)
         _check(lib().bh_tree_export(self.ctx.h, self.h, _ptr(out["keys"]), _ptr(out["perm"]), _ptr(out["level"]),
                                     _ptr(out["first"]), _ptr(out["count"]), _ptr(out["parent"]), _ptr(out["M"]),
-                                    _ptr(out["com"])))
+                                    _ptr(out["com"]), C.byref(nno), _ptr(out["isect_hash"])))
+        if int(nno.value) != nn:
+            raise BHError(E_DEVICE, f"node count changed between bh_tree_info ({nn}) and bh_tree_export ({nno.value})")
         out.update(n_nodes=nn, lo=lo, k=k)
         return out
 
@@ -501,6 +510,10 @@ class Server:
             pass
 
 
+def ic_workspace_bytes():
+    return int(lib().bh_ic_workspace_bytes())
+
+
 def ic_generate(ctx: Context, kind, n, seed, a=1.0, M=1.0):
     """Device-side Plummer (kind 0) or uniform cube (kind 1) initial conditions."""
     torch = _torch()
@@ -508,6 +521,8 @@ def ic_generate(ctx: Context, kind, n, seed, a=1.0, M=1.0):
     pos = torch.empty((n, 3), dtype=torch.float64, device=dev)
     vel = torch.empty((n, 3), dtype=torch.float64, device=dev)
     mass = torch.empty(n, dtype=torch.float64, device=dev)
+    nb = ic_workspace_bytes()
+    _raw, ws = workspace(nb, dev)
     _check(lib().bh_ic_generate(ctx.h, int(kind), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, float(a), float(M),
-                                _ptr(pos), _ptr(vel), _ptr(mass)))
+                                _ptr(pos), _ptr(vel), _ptr(mass), _ptr(ws), nb))
     return pos, vel, mass

@@ -9,6 +9,7 @@
 
 #include "bh.h"
 #include "bh_common.h"
+#include "bh_host.h"
 #include "bh_internal.h"
 
 using namespace bh;
@@ -48,21 +49,6 @@ bh_status bh_check_params(const bh_params *p) {
 
 // ------------------------------------------------------------- planning ---
 
-namespace {
-
-struct Carver {
-    char *base;
-    size_t off = 0;
-    template <typename T>
-    T *take(size_t count) {
-        off = (off + 255) & ~(size_t)255;
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
-
-}  // namespace
 
 // Host tables of a forest membership: segment descriptors (state pointers left
 // null: the concatenated arrays are passed to each launch), sort tiles and walk groups.
@@ -126,58 +112,73 @@ ForestCaps bh_caps_of(const ForestHost &F) {
 }
 
 // Lays out the device buffers for capacities `c` in `ws` (or only measures them when
-// ws == NULL).  Returns the bytes needed.  Counts in F.dev are left untouched.
+// ws == NULL).  Returns the bytes needed (0 when the sizes overflow).  Counts in F.dev
+// are left untouched.
 size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
     ForestDev &D = F.dev;
     const size_t N = cap.ntot, Mc = 2 * (size_t)cap.ntot, S = cap.nseg;
-    size_t scan_len = std::max<size_t>(std::max<size_t>(256 * (size_t)cap.ntiles, N), Mc);
-    Carver c{ws};
-    D.seg = c.take<SegDesc>(S);
-    D.st = c.take<SegState>(S);
-    D.tiles = c.take<TileDesc>(cap.ntiles);
-    D.groups = c.take<GroupDesc>(cap.ngroups);
-    D.segid = c.take<uint32_t>(N);
-    D.keys = c.take<uint64_t>(N);
-    D.keys_alt = c.take<uint64_t>(N);
-    D.idx = c.take<uint32_t>(N);
-    D.idx_alt = c.take<uint32_t>(N);
-    D.cnt = c.take<uint32_t>(256 * (size_t)cap.ntiles + 1);
-    D.segtot = c.take<uint32_t>(256 * S);
-    D.segp = c.take<uint32_t>(256 * S);
-    D.scan_tmp = c.take<uint32_t>(scan_len / 2048 + 2);
-    D.spos = c.take<double>(3 * N);
-    D.smass = c.take<double>(N);
-    D.pk = c.take<double4>(N);
-    D.lcp = c.take<int8_t>(N + 1);
-    D.mask = c.take<uint32_t>(N);
-    D.base = c.take<uint32_t>(N + 1);
-    D.nlevel = c.take<uint8_t>(Mc);
-    D.nchild = c.take<uint32_t>(Mc + 1);
-    D.nfirst = c.take<uint32_t>(Mc);
-    D.ncount = c.take<uint32_t>(Mc);
-    D.nparent = c.take<uint32_t>(Mc);
-    D.ncrank = c.take<uint32_t>(Mc);
-    D.cs = c.take<uint32_t>(Mc + 1);
-    D.slot_of = c.take<uint32_t>(Mc);
-    D.lvl_list = c.take<uint4>(256 * ((Mc + 255) / 256));
-    D.blk_lvl = c.take<uint16_t>((kMaxLevel + 2) * ((Mc + 255) / 256));
-    D.uM = c.take<double>(Mc);
-    D.uS = c.take<double>(3 * Mc);
-    D.rlam = c.take<uint8_t>(N);
-    D.tile_mm = c.take<unsigned long long>(6 * (size_t)cap.ntiles);
-    D.w32 = cap.fp32 ? c.take<WRec32>(Mc) : nullptr;
-    D.w64 = cap.fp64 ? c.take<WRec64>(Mc) : nullptr;
-    D.uQ = cap.quad ? c.take<double>(6 * (size_t)Mc) : nullptr;
-    D.q32 = cap.quad && cap.fp32 ? c.take<float4>(2 * (size_t)Mc) : nullptr;
-    D.q64 = cap.quad && cap.fp64 ? c.take<double>(6 * (size_t)Mc) : nullptr;
-    D.err = c.take<uint32_t>(64);
-    D.stats = c.take<unsigned long long>(8);
-    D.red = c.take<double>(2 * S);
-    D.pot = c.take<double>(N);
+    const size_t scan_len = std::max<size_t>(std::max<size_t>(256 * (size_t)cap.ntiles, N), Mc);
+    const size_t blocks = (Mc + 255) / 256;
+    // (pointer, count, element size) in carve order
+    struct Slot {
+        void **p;
+        size_t count, elem;
+    };
+    const Slot slots[] = {
+        {(void **)&D.seg, S, sizeof(SegDesc)},
+        {(void **)&D.st, S, sizeof(SegState)},
+        {(void **)&D.tiles, cap.ntiles, sizeof(TileDesc)},
+        {(void **)&D.groups, cap.ngroups, sizeof(GroupDesc)},
+        {(void **)&D.segid, N, 4},
+        {(void **)&D.keys, N, 8},
+        {(void **)&D.keys_alt, N, 8},
+        {(void **)&D.idx, N, 4},
+        {(void **)&D.idx_alt, N, 4},
+        {(void **)&D.cnt, 256 * (size_t)cap.ntiles + 1, 4},
+        {(void **)&D.segtot, 256 * S, 4},
+        {(void **)&D.segp, 256 * S, 4},
+        {(void **)&D.scan_tmp, scan_len / 2048 + 2, 4},
+        {(void **)&D.spos, 3 * N, 8},
+        {(void **)&D.smass, N, 8},
+        {(void **)&D.pk, N, sizeof(double4)},
+        {(void **)&D.lcp, N + 1, 1},
+        {(void **)&D.mask, N, 4},
+        {(void **)&D.base, N + 1, 4},
+        {(void **)&D.nlevel, Mc, 1},
+        {(void **)&D.nchild, Mc + 1, 4},
+        {(void **)&D.nfirst, Mc, 4},
+        {(void **)&D.ncount, Mc, 4},
+        {(void **)&D.nparent, Mc, 4},
+        {(void **)&D.ncrank, Mc, 4},
+        {(void **)&D.cs, Mc + 1, 4},
+        {(void **)&D.slot_of, Mc, 4},
+        {(void **)&D.lvl_list, 256 * blocks, sizeof(uint4)},
+        {(void **)&D.blk_lvl, (kMaxLevel + 2) * blocks, 2},
+        {(void **)&D.uM, Mc, 8},
+        {(void **)&D.uS, 3 * Mc, 8},
+        {(void **)&D.rlam, N, 1},
+        {(void **)&D.tile_mm, 6 * (size_t)cap.ntiles, 8},
+        {(void **)&D.w32, cap.fp32 ? Mc : 0, sizeof(WRec32)},
+        {(void **)&D.w64, cap.fp64 ? Mc : 0, sizeof(WRec64)},
+        {(void **)&D.uQ, cap.quad ? 6 * Mc : 0, 8},
+        {(void **)&D.q32, cap.quad && cap.fp32 ? 2 * Mc : 0, sizeof(float4)},
+        {(void **)&D.q64, cap.quad && cap.fp64 ? 6 * Mc : 0, 8},
+        {(void **)&D.err, 64, 4},
+        {(void **)&D.stats, 8, 8},
+        {(void **)&D.red, 2 * S, 8},
+        {(void **)&D.pot, N, 8},
+    };
+    std::vector<bh_host::Region> regions;
+    for (const Slot &sl : slots) regions.push_back(bh_host::Region{sl.count, sl.elem});
+    std::vector<size_t> off;
+    size_t total = 0;
+    if (!bh_host::layout(regions, off, total)) return 0;
+    for (size_t i = 0; i < regions.size(); ++i)
+        *slots[i].p = (ws && regions[i].count) ? (void *)(ws + off[i]) : nullptr;
     F.caps = cap;
     F.ws = ws;
-    F.ws_bytes = c.off + 256;
-    return c.off + 256;
+    F.ws_bytes = total;
+    return total;
 }
 
 size_t bh_plan_forest(ForestHost &F, int32_t nseg, const int64_t *n, const bh_params *p, char *ws) {
@@ -222,6 +223,7 @@ bh_status bh_forest_init(bh_ctx *ctx, ForestHost &F, int32_t nseg, const int64_t
     if (!ws) return bh_fail(BH_E_INVAL, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return bh_fail(BH_E_INVAL, "workspace must be 256-byte aligned");
     size_t need = bh_plan_forest(F, nseg, n, p, nullptr);
+    if (need == 0) return bh_fail(BH_E_NOMEM, "workspace size overflows");
     if (ws_bytes < need) return bh_fail(BH_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     bh_plan_forest(F, nseg, n, p, (char *)ws);
     F.ctx = ctx;
@@ -274,15 +276,40 @@ bh_status bh_forest_kdk_steps(ForestHost &F, double *pos, double *vel, const dou
     return BH_OK;
 }
 
+void bh_ctx_attach(bh_ctx *ctx, ForestHost *F) {
+    if (ctx) ctx->live.push_back(F);
+}
+
+void bh_ctx_detach(bh_ctx *ctx, ForestHost *F) {
+    if (!ctx) return;
+    for (size_t i = 0; i < ctx->live.size(); ++i)
+        if (ctx->live[i] == F) {
+            ctx->live.erase(ctx->live.begin() + (long)i);
+            return;
+        }
+}
+
+// Reports the fault bits gathered since the last report, and clears them.
 bh_status bh_forest_check_err(ForestHost &F) {
     uint32_t e = 0;
     HIPCHK(hipMemcpyAsync(&e, F.dev.err, sizeof(uint32_t), hipMemcpyDeviceToHost, F.ctx->stream));
     HIPCHK(hipStreamSynchronize(F.ctx->stream));
+    if (e) HIPCHK(launch_fill_u32(F.dev.err, 0, 1, F.ctx->stream));
     if (e & kErrStack) return bh_fail(BH_E_OVERFLOW, "walk stack overflow");
     if (e & kErrTree) return bh_fail(BH_E_DEVICE, "inconsistent tree detected on the device");
-    if (e & kErrNonFinite) return bh_fail(BH_E_DEVICE, "device fault flag: non-finite state or generator failure");
+    if (e & kErrNonFinite) return bh_fail(BH_E_DEVICE, "device fault flag: non-finite position or mass");
     return BH_OK;
 }
+
+namespace {
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+}  // namespace
 
 // ---------------------------------------------------------------- context ---
 
@@ -301,18 +328,6 @@ bh_status bh_ctx_create(int device, void *hip_stream, bh_ctx **out) {
     if (!c) return bh_fail(BH_E_NOMEM, "host allocation failed");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    // small library scratch for the initial-condition reductions and their fault flag
-    hipError_t e = hipMalloc((void **)&c->scratch, sizeof(double) * (6 * 256 + 8));
-    if (e != hipSuccess) {
-        delete c;
-        return bh_fail(BH_E_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    e = hipMemset(c->scratch, 0, sizeof(double) * (6 * 256 + 8));
-    if (e != hipSuccess) {
-        (void)hipFree(c->scratch);
-        delete c;
-        return bh_fail(BH_E_DEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
-    }
     *out = c;
     return BH_OK;
 }
@@ -321,7 +336,7 @@ bh_status bh_ctx_destroy(bh_ctx *ctx) {
     if (!ctx) return BH_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(ctx->scratch);
+    for (ForestHost *F : ctx->live) F->ctx = nullptr;   // handles outliving their context
     delete ctx;
     return BH_OK;
 }
@@ -329,6 +344,10 @@ bh_status bh_ctx_destroy(bh_ctx *ctx) {
 bh_status bh_ctx_sync(bh_ctx *ctx) {
     if (!ctx) return bh_fail(BH_E_INVAL, "ctx is NULL");
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (ForestHost *F : ctx->live) {
+        bh_status st = bh_forest_check_err(*F);
+        if (st != BH_OK) return st;
+    }
     return BH_OK;
 }
 
@@ -359,6 +378,7 @@ bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass
         delete t;
         return bh_fail(BH_E_DEVICE, std::string("build launch: ") + hipGetErrorString(e));
     }
+    bh_ctx_attach(ctx, &t->F);
     *out = t;
     return BH_OK;
 }
@@ -385,30 +405,9 @@ bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
 
 namespace {
 
-struct ListLayout {
-    size_t head, count, next, ent, total;
-};
-
-size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-ListLayout list_layout(size_t ngroups, size_t nchunks) {
-    ListLayout l;
-    l.head = 256 * kListParts;
-    l.count = up256(l.head + 4 * ngroups);
-    l.next = up256(l.count + 4 * ngroups);
-    l.ent = up256(l.next + 4 * nchunks);
-    l.total = l.ent + sizeof(bh_list_entry) * 64 * nchunks;
-    return l;
-}
-
-// largest chunk count whose layout fits in `bytes` (0 also when not even the tables fit)
-size_t list_chunks_for(size_t ngroups, size_t bytes) {
-    const size_t fixed = list_layout(ngroups, 0).total;
-    if (bytes <= fixed + 256) return 0;
-    size_t c = (bytes - fixed - 256) / (4 + sizeof(bh_list_entry) * 64);
-    while (c > 0 && list_layout(ngroups, c).total > bytes) --c;
-    return c > 0xffffffffu ? 0xffffffffu : c;
-}
+using bh_host::list_chunks_for;
+using bh_host::list_layout;
+using bh_host::ListLayout;
 
 ListDev list_dev(void *buf, size_t ngroups, size_t nchunks) {
     const ListLayout l = list_layout(ngroups, nchunks);
@@ -431,7 +430,8 @@ bh_status lists_supported(const bh_tree *t) {
 
 }  // namespace
 
-static_assert(sizeof(bh_list_entry) == 16, "list entries are 16 bytes");
+static_assert(sizeof(bh_list_entry) == bh_host::kListEntryBytes && kListParts == bh_host::kListPartitions,
+              "list layout constants");
 
 bh_status bh_lists_build(bh_ctx *ctx, bh_tree *t, void *buf, size_t bytes, size_t *bytes_needed) {
     if (!ctx || !t || !buf) return bh_fail(BH_E_INVAL, "NULL argument");
@@ -491,13 +491,20 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
                           uint64_t *hash, bh_stats *totals) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
     HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
+    HIPCHK(hipEventRecord(ev.a, ctx->stream));
     HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream,
                        t->F.walk_waves));
+    HIPCHK(hipEventRecord(ev.b, ctx->stream));
     unsigned long long h[8];
     HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     bh_status st = bh_forest_check_err(t->F);
     if (st != BH_OK) return st;
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
     if (totals) {
         totals->n_mono = h[0];
         totals->n_p2p = h[1];
@@ -507,6 +514,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
         totals->wave_entries = h[5];
         totals->wave_accepts = h[6];
         totals->wave_leaves = h[7];
+        totals->t_ms = ms;
     }
     return BH_OK;
 }
@@ -565,14 +573,27 @@ bh_status bh_tree_info(bh_ctx *ctx, bh_tree *t, int64_t *n_nodes, double lo[3], 
 }
 
 bh_status bh_tree_export(bh_ctx *ctx, bh_tree *t, uint64_t *keys, uint32_t *perm, int32_t *level, uint32_t *first,
-                         uint32_t *count, int32_t *parent, double *M, double *com) {
+                         uint32_t *count, int32_t *parent, double *M, double *com, int64_t *n_nodes,
+                         uint64_t *isect_hash) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
-    if ((M || com) && !t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before exporting M/com");
+    if ((M || com || isect_hash) && !t->upward_done)
+        return bh_fail(BH_E_INVAL, "bh_upward must run before exporting M, com or the checksums");
     HIPCHK(launch_export(t->F.dev, 0, keys, perm, level, first, count, parent, M, com, ctx->stream));
+    if (isect_hash)   // the counting walk, writing only the per-body checksums
+        HIPCHK(launch_walk(t->F.dev, true, false, nullptr, nullptr, nullptr, nullptr, isect_hash, ctx->stream,
+                           t->F.walk_waves));
+    if (n_nodes || isect_hash) {
+        SegState st;
+        HIPCHK(hipMemcpyAsync(&st, t->F.dev.st, sizeof(SegState), hipMemcpyDeviceToHost, ctx->stream));
+        bh_status rs = bh_forest_check_err(t->F);
+        if (rs != BH_OK) return rs;
+        if (n_nodes) *n_nodes = st.nn;
+    }
     return BH_OK;
 }
 
 bh_status bh_tree_free(bh_ctx *ctx, bh_tree *t) {
+    if (t) bh_ctx_detach(t->F.ctx, &t->F);
     (void)ctx;
     delete t;
     return BH_OK;
@@ -598,6 +619,7 @@ bh_status bh_sim_create(bh_ctx *ctx, int64_t n, double *pos, double *vel, const 
     sm->vel = vel;
     sm->mass = mass;
     sm->acc = acc;
+    bh_ctx_attach(ctx, &sm->F);
     *out = sm;
     return BH_OK;
 }
@@ -634,6 +656,7 @@ bh_status bh_energy(bh_ctx *ctx, bh_sim *sm, double out_KW[2]) {
 }
 
 bh_status bh_sim_destroy(bh_ctx *ctx, bh_sim *sm) {
+    if (sm) bh_ctx_detach(sm->F.ctx, &sm->F);
     (void)ctx;
     delete sm;
     return BH_OK;
@@ -663,6 +686,7 @@ bh_status bh_forest_create(bh_ctx *ctx, int32_t n_sims, const int64_t *n, const 
     fo->vel = vel;
     fo->mass = mass;
     fo->acc = acc;
+    bh_ctx_attach(ctx, &fo->F);
     *out = fo;
     return BH_OK;
 }
@@ -738,15 +762,6 @@ bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const
     return BH_OK;
 }
 
-namespace {
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~EventPair() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
-}  // namespace
 
 bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, int32_t *waves_out, double *ms_out) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
@@ -794,6 +809,7 @@ bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, int32_t *waves_out, dou
 bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *fo) {
     (void)ctx;
     if (!fo) return BH_OK;
+    bh_ctx_detach(fo->F.ctx, &fo->F);
     if (fo->graph) (void)hipGraphExecDestroy(fo->graph);
     if (fo->cap_stream) (void)hipStreamDestroy(fo->cap_stream);
     delete fo;
@@ -813,14 +829,28 @@ bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *fo, double *out_KW) {
 
 // ---------------------------------------------------- initial conditions ---
 
+// Workspace of bh_ic_generate: the generator's partial sums, then its fault word.
+static size_t ic_flag_offset() { return (ic_scratch_bytes() + 255) & ~(size_t)255; }
+
+size_t bh_ic_workspace_bytes(void) { return ic_flag_offset() + 256; }
+
 bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M, double *pos,
-                         double *vel, double *mass) {
-    if (!ctx || !pos || !vel || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+                         double *vel, double *mass, void *ws, size_t ws_bytes) {
+    if (!ctx || !pos || !vel || !mass || !ws) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (((uintptr_t)ws & 255) != 0) return bh_fail(BH_E_INVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < bh_ic_workspace_bytes())
+        return bh_fail(BH_E_NOMEM, "workspace too small: need " + std::to_string(bh_ic_workspace_bytes()) + " bytes");
     if (kind != 0 && kind != 1) return bh_fail(BH_E_INVAL, "kind must be 0 (Plummer) or 1 (cube)");
     if (n < 1 || n > (int64_t)0x3fffffff) return bh_fail(BH_E_INVAL, "n out of range");
     if (!(a > 0.0) || !(M > 0.0) || !std::isfinite(a) || !std::isfinite(M))
         return bh_fail(BH_E_INVAL, "a and M must be positive and finite");
-    HIPCHK(launch_ic(kind, n, seed, a, M, pos, vel, mass, ctx->scratch, ctx->stream));
+    uint32_t *flag = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + ic_flag_offset());
+    HIPCHK(launch_fill_u32(flag, 0, 1, ctx->stream));
+    HIPCHK(launch_ic(kind, n, seed, a, M, pos, vel, mass, static_cast<double *>(ws), flag, ctx->stream));
+    uint32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, flag, sizeof(e), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (e) return bh_fail(BH_E_DEVICE, "initial conditions: a velocity draw found no acceptance in 401 tries");
     return BH_OK;
 }
 

@@ -39,7 +39,6 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
 // enough loads are in flight with one tile per compute unit.
 constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = kTile / kSortThreads;
 
 // Inclusive scan of one value per thread over the block (any multiple of 64
 // threads; lds_waves holds one entry per wavefront).
@@ -198,7 +197,10 @@ __global__ void __launch_bounds__(kSortThreads) k_bbox(ForestDev f, const double
     const double *pb = seg_base(pos, sd.pos, sd, 3);
     const double *mb = seg_base(mass, sd.mass, sd, 1);
     const uint32_t j0 = td.start - sd.start;
+    // a new build: the previous tree's inconsistency flag no longer applies
+    if (blockIdx.x == 0 && threadIdx.x == 0) f.err[kErrWordTree] = 0;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
     for (uint32_t j = threadIdx.x; j < td.count; j += kSortThreads) {
         size_t i = (size_t)j0 + j;
         double v[3];
@@ -208,9 +210,13 @@ __global__ void __launch_bounds__(kSortThreads) k_bbox(ForestDev f, const double
             mn[d] = fmin(mn[d], v[d]);
             mx[d] = fmax(mx[d], v[d]);
         }
+        const double m = mb[i];
+        bad |= !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]) || !isfinite(m);
         // the particle as one aligned record, for the gather into key order
-        f.pk[(size_t)td.start + j] = make_double4(v[0], v[1], v[2], mb[i]);
+        f.pk[(size_t)td.start + j] = make_double4(v[0], v[1], v[2], m);
     }
+    // a non-finite coordinate or mass (fmin/fmax would pass over a NaN) is reported
+    if (__builtin_amdgcn_ballot_w64(bad) && (threadIdx.x & 63) == 0) atomicOr(f.err, kErrNonFinite);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -502,7 +508,7 @@ __global__ void k_permute_lcp(ForestDev f) {
         }
         const size_t li = f.idx[r] - sd.start;
         if (li >= sd.n) {   // cannot happen after a correct sort
-            atomicOr(f.err, kErrTree);
+            flag_tree(f);
         } else {
             const double4 p = f.pk[sd.start + li];
             f.spos[3 * (size_t)r] = p.x;
@@ -623,7 +629,7 @@ __global__ void __launch_bounds__(256) k_fill(ForestDev f) {
             // the leaf starting at r, if any: the deepest node starting at r
             const int lam = f.rlam[r];
             if (lam > kMaxLevel || m >> lam != 1u) {
-                atomicOr(f.err, kErrTree);   // the deepest node starting at a row must be its leaf
+                flag_tree(f);   // the deepest node starting at a row must be its leaf
             } else {
                 const uint32_t g = node_id(f, r, lam);
                 f.nlevel[g] = (uint8_t)lam;
@@ -660,7 +666,7 @@ __global__ void __launch_bounds__(256) k_link(ForestDev f) {
         c = f.base[e];
     }
     if (bad || k < 2) {
-        atomicOr(f.err, kErrTree);
+        flag_tree(f);
         k = 0;
     }
     f.nchild[g] = k;
@@ -694,7 +700,7 @@ __global__ void __launch_bounds__(256) k_slots(ForestDev f) {
             sl = f.nseg + f.cs[p] + rk;
         }
         if (sl >= mtot) {
-            atomicOr(f.err, kErrTree);
+            flag_tree(f);
         } else {
             f.slot_of[g] = sl;
             const uint32_t nc = f.nchild[g];
@@ -770,7 +776,7 @@ __global__ void k_up_leaf(ForestDev f) {
     if (g >= mtot || f.nchild[g] != 0) return;
     const uint32_t a = f.nfirst[g], b = a + f.ncount[g];
     const uint32_t sl = f.slot_of[g];
-    if (a >= f.ntot || b > f.ntot || b <= a || sl >= mtot) { atomicOr(f.err, kErrTree); return; }
+    if (a >= f.ntot || b > f.ntot || b <= a || sl >= mtot) { flag_tree(f); return; }
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     for (uint32_t r = a; r < b; ++r) {
         const double m = f.smass[r];
@@ -813,7 +819,7 @@ __global__ void __launch_bounds__(256) k_up_level(ForestDev f, int level, uint32
         for (uint32_t i = begin + lane; i < end; i += 64) {
             const uint4 e = f.lvl_list[(size_t)b * 256 + i];
             const uint32_t sl = e.x, c0 = e.y, nc = e.z;
-            if (sl >= mtot || nc < 2 || nc > 8 || c0 + nc > mtot) { atomicOr(f.err, kErrTree); continue; }
+            if (sl >= mtot || nc < 2 || nc > 8 || c0 + nc > mtot) { flag_tree(f); continue; }
             double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
             for (uint32_t k = 0; k < nc; ++k) {
                 const size_t c = c0 + k;
@@ -834,6 +840,8 @@ __global__ void __launch_bounds__(256) k_up_level(ForestDev f, int level, uint32
                 for (uint32_t k = 0; k < nc; ++k) {
                     const size_t c = c0 + k;
                     const double mc = f.uM[c];
+                    // a massless child adds nothing (its own centre, 0/0, is undefined)
+                    if (mc == 0.0) continue;
                     const double x = f.uS[3 * c] / mc - cx, y = f.uS[3 * c + 1] / mc - cy,
                                  z = f.uS[3 * c + 2] / mc - cz;
                     const double *qc = f.uQ + 6 * c;
@@ -890,7 +898,7 @@ __global__ void k_records(ForestDev f) {
     if (g >= mtot) return;
     const uint32_t sl = f.slot_of[g];
     if (sl >= mtot) {
-        atomicOr(f.err, kErrTree);
+        flag_tree(f);
         return;
     }
     const double M = f.uM[sl];
@@ -905,7 +913,7 @@ __global__ void k_records(ForestDev f) {
     const uint32_t cnt = nc ? nc : (f.ncount[g] | kLeafBit);
     if ((nc && (nc < 2 || nc > 8 || link + nc > mtot)) ||
         (!nc && (link >= f.ntot || f.ncount[g] == 0 || link + f.ncount[g] > f.ntot))) {
-        atomicOr(f.err, kErrTree);
+        flag_tree(f);
         return;
     }
     const double s = ldexp(st.L, -level);

@@ -14,10 +14,13 @@ constexpr int kStackMax = 160;         // >= 1 + 7 * 21 entries of (child block,
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
 
-// error word bits
+// Device error words (ForestDev::err).  Word 0 gathers the fault bits until a
+// synchronising call reports and clears them; word 1 holds kErrTree for the
+// current tree only (cleared by every build): the walks skip an inconsistent tree.
 constexpr uint32_t kErrStack = 1u;
-constexpr uint32_t kErrNonFinite = 2u;
-constexpr uint32_t kErrTree = 4u;      // inconsistent tree: the walk is skipped
+constexpr uint32_t kErrNonFinite = 2u;  // non-finite position or mass, or a failed generator draw
+constexpr uint32_t kErrTree = 4u;       // inconsistent tree
+constexpr int kErrWordTree = 1;
 
 // Per simulation, fixed while its membership in a forest lasts (host written).
 struct SegDesc {
@@ -123,6 +126,12 @@ struct ForestDev {
 };
 
 // ---------------------------------------------------------------- helpers ---
+
+// An inconsistent tree: reported, and its walks skipped.
+__device__ __forceinline__ void flag_tree(const ForestDev &f) {
+    atomicOr(f.err, kErrTree);
+    atomicOr(f.err + kErrWordTree, kErrTree);
+}
 
 // Walk variant of a simulation: expansion order and whether its FP32 softening is zero
 // (one bit each of ForestDev::has32 / has64; the FP64 walk ignores the softening bit).
@@ -293,8 +302,11 @@ hipError_t launch_energy(const ForestDev &f, const double *vel, const double *ma
 hipError_t launch_export(const ForestDev &f, uint32_t seg, uint64_t *keys, uint32_t *perm, int32_t *level,
                          uint32_t *first, uint32_t *count, int32_t *parent, double *M, double *com,
                          hipStream_t s);
+// Initial conditions; part: ic_scratch_bytes() of partial sums; err: the word that
+// receives kErrNonFinite when a velocity draw fails.
+size_t ic_scratch_bytes();
 hipError_t launch_ic(int kind, int64_t n, uint64_t seed, double a, double M, double *pos, double *vel,
-                     double *mass, double *scratch, hipStream_t s);
+                     double *mass, double *part, uint32_t *err, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_segid(const ForestDev &f, hipStream_t s);
 

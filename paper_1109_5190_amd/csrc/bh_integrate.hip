@@ -140,6 +140,7 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
 }
 
 constexpr uint32_t kPlummerTag = 1, kCubeTag = 2;
+constexpr uint32_t kIcBlocks = 256;   // blocks of the generator: one partial-sum record (6 FP64) each
 constexpr double kMassCut = 0.999;
 
 __device__ inline void draw2(uint64_t i, uint32_t call, uint32_t tag, uint64_t seed, double &u0, double &u1) {
@@ -229,12 +230,12 @@ __global__ void k_ic_shift(int64_t n, double M, double *pos, double *vel, const 
     }
 }
 
+size_t ic_scratch_bytes() { return sizeof(double) * 6 * kIcBlocks; }
+
 hipError_t launch_ic(int kind, int64_t n, uint64_t seed, double a, double M, double *pos, double *vel,
-                     double *mass, double *scratch, hipStream_t s) {
-    const int nblk = 256;
-    hipLaunchKernelGGL(k_ic, dim3(nblk), dim3(256), 0, s, kind, n, seed, a, M, pos, vel, mass, scratch,
-                       (uint32_t *)(scratch + 6 * nblk));
-    if (kind == 0) hipLaunchKernelGGL(k_ic_shift, dim3(512), dim3(256), 0, s, n, M, pos, vel, scratch, nblk);
+                     double *mass, double *part, uint32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_ic, dim3(kIcBlocks), dim3(256), 0, s, kind, n, seed, a, M, pos, vel, mass, part, err);
+    if (kind == 0) hipLaunchKernelGGL(k_ic_shift, dim3(512), dim3(256), 0, s, n, M, pos, vel, part, (int)kIcBlocks);
     return hipGetLastError();
 }
 

@@ -6,10 +6,12 @@
 #include "bh.h"
 #include "bh_common.h"
 
+struct ForestHost;
+
 struct bh_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    double *scratch = nullptr;   // initial-condition reductions (6 x 256 doubles) + fault flag
+    std::vector<ForestHost *> live;   // trees, simulations and forests of this context (fault words)
 };
 
 struct ForestCaps {
@@ -72,3 +74,6 @@ bh_status bh_forest_kdk(ForestHost &F, double *pos, double *vel, const double *m
 bh_status bh_forest_kdk_steps(ForestHost &F, double *pos, double *vel, const double *mass, double *acc,
                               int32_t nsteps, hipStream_t s);
 bh_status bh_forest_check_err(ForestHost &F);
+// Membership of a tree, simulation or forest in its context's list (bh_ctx_sync reports their faults).
+void bh_ctx_attach(bh_ctx *ctx, ForestHost *F);
+void bh_ctx_detach(bh_ctx *ctx, ForestHost *F);

@@ -26,12 +26,11 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     WaveLds32 &L = lds_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
-    if (uni(*f.err) & kErrTree) return;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
     if (sd.precision != 1 || sd.group) return;   // refused by the host
-    const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
@@ -163,7 +162,7 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
     float4 *mst = mst_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
-    if (uni(*f.err) & (kErrTree | kErrStack)) return;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
@@ -390,7 +389,7 @@ __global__ void __launch_bounds__(64 * W) k_lists64(ForestDev f, ListDev ld) {
     WaveLds64<false> &L = lds_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
-    if (uni(*f.err) & kErrTree) return;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
@@ -489,7 +488,7 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
     double4 *mst = mst_all[wave];
     const uint32_t gi = blockIdx.x * 4 + wave;
     if (gi >= f.ngroups) return;
-    if (uni(*f.err) & (kErrTree | kErrStack)) return;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];

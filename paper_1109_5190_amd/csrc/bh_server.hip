@@ -26,6 +26,7 @@
 
 #include "bh.h"
 #include "bh_common.h"
+#include "bh_host.h"
 #include "bh_internal.h"
 
 using namespace bh;
@@ -36,44 +37,6 @@ enum { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3, kCancelled = 4 };
 constexpr uint32_t kReqReleaseAtEnd = 1u;   // bh_params.flags bit: free the state when done (no fetch)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// First-fit allocator over byte offsets of the arena (host bookkeeping only).
-struct Arena {
-    std::map<size_t, size_t> free_;   // offset -> bytes
-    void init(size_t off, size_t bytes) {
-        free_.clear();
-        if (bytes) free_[off] = bytes;
-    }
-    bool alloc(size_t bytes, size_t &off) {
-        bytes = align256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                off = it->first;
-                size_t rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align256(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 struct Req {
     uint64_t id = 0;
@@ -96,11 +59,11 @@ struct bh_server {
     bh_ctx sctx;                 // the server's own context (its stream)
     char *arena = nullptr;
     size_t arena_bytes = 0, ws_bytes = 0;
-    double *scratch = nullptr;   // initial-condition reductions
+    double *scratch = nullptr;   // initial-condition reductions (partial sums)
     int32_t max_slots = 0;
     int64_t max_resident = 0;
     ForestHost F;
-    Arena mem;
+    bh_host::Arena mem;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<uint64_t> queue;
@@ -217,18 +180,19 @@ void bh_server::loop() {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
                 // admission, first come first served: stop at the first request that does not fit
-                while (!queue.empty()) {
-                    Req &q = reqs[queue.front()];
-                    if (q.state == kCancelled) {
-                        queue.pop_front();
-                        continue;
-                    }
-                    if ((int32_t)resident.size() >= max_slots || resident_particles + q.r.n > max_resident) break;
-                    size_t off;
-                    if (!mem.alloc(q.bytes, off)) break;
-                    q.off = off;
+                int32_t slots = (int32_t)resident.size();
+                const auto admitted = bh_host::admit_fcfs(
+                    queue,
+                    [this](uint64_t id) {
+                        const Req &q = reqs[id];
+                        return bh_host::Queued{q.r.n, q.bytes, q.state == kCancelled};
+                    },
+                    bh_host::Caps{max_slots, max_resident}, slots, resident_particles, mem);
+                for (const auto &ad : admitted) {
+                    Req &q = reqs[ad.first];
+                    q.off = ad.second;
                     q.has_mem = true;
-                    char *b = arena + off;
+                    char *b = arena + q.off;
                     const size_t n = (size_t)q.r.n;
                     q.pos = (double *)b;
                     q.vel = q.pos + 3 * n;
@@ -239,9 +203,7 @@ void bh_server::loop() {
                     q.t_admit = now();
                     q.fresh = true;
                     resident.push_back(q.id);
-                    resident_particles += q.r.n;
                     fresh.push_back(q.id);
-                    queue.pop_front();
                 }
                 if (!resident.empty()) break;
                 if (stop) return;
@@ -249,21 +211,23 @@ void bh_server::loop() {
             }
             ids = resident;
         }
-        bool ok = true;
+        // the error word covers this iteration only: initial conditions, tree, walk
+        bool ok = launch_fill_u32(F.dev.err, 0, 64, stream) == hipSuccess;
         for (uint64_t id : fresh) {
             Req *q;
             {
                 std::lock_guard<std::mutex> lk(mu);
                 q = &reqs[id];
             }
-            if (launch_ic(q->r.ic_kind, q->r.n, q->r.seed, 1.0, 1.0, q->pos, q->vel, q->mass, scratch, stream) !=
-                hipSuccess)
+            if (ok && launch_ic(q->r.ic_kind, q->r.n, q->r.seed, 1.0, 1.0, q->pos, q->vel, q->mass, scratch,
+                                F.dev.err, stream) != hipSuccess)
                 ok = false;
         }
         if (ok) ok = iterate(ids);
         if (!ok) {
             std::lock_guard<std::mutex> lk(mu);
-            fault = "device error in a server iteration";
+            fault = "device error or fault flag (non-finite state, generator failure, inconsistent tree) "
+                    "in a server iteration";
             for (uint64_t id : ids) {
                 Req &q = reqs[id];
                 q.state = kFailed;
@@ -303,8 +267,8 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     cap.fp32 = cap.fp64 = true;
     cap.quad = true;
     size_t ws = bh_forest_carve(sv->F, cap, nullptr);
-    size_t scratch_bytes = align256(sizeof(double) * (6 * 256 + 8));
-    if (ws + scratch_bytes >= arena_bytes) {
+    const size_t scratch_bytes = align256(ic_scratch_bytes());
+    if (ws == 0 || ws + scratch_bytes >= arena_bytes) {
         delete sv;
         return bh_fail(BH_E_NOMEM, "arena too small for the tree workspace: need more than " +
                                        std::to_string(ws + scratch_bytes) + " bytes");
@@ -323,7 +287,6 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     sv->sctx.stream = sv->stream;
     sv->F.ctx = &sv->sctx;
     e = launch_fill_u32(sv->F.dev.err, 0, 64, sv->stream);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)sv->scratch, 0, (uint32_t)(scratch_bytes / 4), sv->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(sv->stream);
@@ -343,7 +306,7 @@ bh_status bh_server_submit(bh_server *sv, const bh_request *req, uint64_t *id) {
     bh_status st = bh_check_params(&req->p);
     if (st != BH_OK) return st;
     const size_t bytes = state_bytes(req->n);
-    if (req->n > sv->max_resident || bytes > sv->arena_bytes - sv->ws_bytes)
+    if (bh_host::never_fits(req->n, bytes, bh_host::Caps{sv->max_slots, sv->max_resident}, sv->mem))
         return bh_fail(BH_E_NOMEM, "request can never fit the server's arena or particle cap");
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) return bh_fail(BH_E_INVAL, "server is shutting down");

@@ -13,7 +13,7 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     WaveLds64<QUAD> &L = lds_all[wave];
     const uint32_t gi = blockIdx.x * W + wave;
     if (gi >= f.ngroups) return;
-    if (uni(*f.err) & kErrTree) return;   // tree inconsistent: never walk it
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;   // tree inconsistent: never walk it
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
@@ -177,9 +177,11 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
         const size_t li = i - sd.start;
         const double G = sd.G;
         double *accb = seg_base(out.acc, sd.acc, sd, 3);
-        accb[3 * li] = G * ax;
-        accb[3 * li + 1] = G * ay;
-        accb[3 * li + 2] = G * az;
+        if (accb) {   // null: a counting walk for the checksums only
+            accb[3 * li] = G * ax;
+            accb[3 * li + 1] = G * ay;
+            accb[3 * li + 2] = G * az;
+        }
         if (POT) {
             double *potb = seg_base(out.pot, sd.pot, sd, 1);
             if (potb) potb[li] = G * ap;

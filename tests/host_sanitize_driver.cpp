@@ -1,0 +1,209 @@
+// Exercises the library's host-only logic (workspace layouts, interaction-list
+// buffer layouts, the server's first-fit arena and its first-come first-served
+// admission) for a build under AddressSanitizer and UndefinedBehaviorSanitizer,
+// and checks its invariants against plain reference models.  Test
+// infrastructure: exit status 0 and "all cases ok" when every check holds.
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <deque>
+#include <map>
+#include <random>
+#include <vector>
+
+#include "../paper_1109_5190_amd/csrc/bh_host.h"
+
+using namespace bh_host;
+
+static int failures = 0;
+#define CHECK(c)                                                          \
+    do {                                                                  \
+        if (!(c)) {                                                       \
+            std::fprintf(stderr, "check failed at line %d: %s\n", __LINE__, #c); \
+            ++failures;                                                   \
+        }                                                                 \
+    } while (0)
+
+static void layouts(std::mt19937_64 &rng) {
+    for (int t = 0; t < 2000; ++t) {
+        std::vector<Region> r(1 + rng() % 48);
+        for (auto &x : r) {
+            x.count = (rng() % 4 == 0) ? 0 : rng() % 100000;
+            x.elem = 1 + rng() % 64;
+        }
+        std::vector<size_t> off;
+        size_t total = 0;
+        CHECK(layout(r, off, total));
+        size_t end = 0;
+        for (size_t i = 0; i < r.size(); ++i) {
+            CHECK(off[i] % kAlign == 0);
+            CHECK(off[i] >= end);
+            end = off[i] + r[i].count * r[i].elem;
+        }
+        CHECK(total >= end + kAlign - 1 && total % 1 == 0);
+    }
+    // sizes that overflow are refused, not wrapped
+    std::vector<size_t> off;
+    size_t total = 7;
+    CHECK(!layout({{SIZE_MAX / 2, 4}}, off, total));
+    CHECK(!layout({{SIZE_MAX / 16, 8}, {SIZE_MAX / 16, 8}, {SIZE_MAX / 16, 8}}, off, total));
+    CHECK(total == 7);
+    size_t a;
+    CHECK(!align_up(SIZE_MAX - 3, a));
+    CHECK(align_up(0, a) && a == 0);
+    CHECK(align_up(1, a) && a == 256);
+}
+
+static void list_layouts(std::mt19937_64 &rng) {
+    for (int t = 0; t < 3000; ++t) {
+        const size_t ng = rng() % 200000;
+        const size_t bytes = rng() % (size_t(1) << 30);
+        const size_t c = list_chunks_for(ng, bytes);
+        const ListLayout l = list_layout(ng, c);
+        CHECK(l.head % kAlign == 0 && l.count % kAlign == 0 && l.next % kAlign == 0 && l.ent % kAlign == 0);
+        CHECK(l.count >= l.head + 4 * ng && l.next >= l.count + 4 * ng && l.ent >= l.next + 4 * c);
+        if (c > 0) CHECK(l.total <= bytes);
+        if (c < 0xffffffffu && bytes > list_layout(ng, 0).total + kAlign)
+            CHECK(list_layout(ng, c + 1).total > bytes - kAlign);
+    }
+}
+
+// Arena against a bitmap of 256-byte units.
+static void arena(std::mt19937_64 &rng) {
+    for (int t = 0; t < 200; ++t) {
+        const size_t base = (rng() % 64) * kAlign;
+        const size_t units = 1 + rng() % 4096;
+        const size_t bytes = units * kAlign + rng() % kAlign;   // a ragged tail is never handed out
+        Arena A;
+        A.init(base, bytes);
+        CHECK(A.capacity() == units * kAlign);
+        std::vector<char> used(units, 0);
+        std::map<size_t, size_t> live;   // offset -> requested bytes
+        for (int op = 0; op < 3000; ++op) {
+            if (live.empty() || rng() % 3) {
+                const size_t want = 1 + rng() % (units * kAlign / 4 + 1);
+                size_t off = 0;
+                if (A.alloc(want, off)) {
+                    size_t b;
+                    CHECK(align_up(want, b));
+                    CHECK(off >= base && off % kAlign == 0 && off + b <= base + units * kAlign);
+                    for (size_t u = (off - base) / kAlign; u < (off - base + b) / kAlign; ++u) {
+                        CHECK(!used[u]);
+                        used[u] = 1;
+                    }
+                    live[off] = want;
+                } else {
+                    // first fit: no free run of that many units exists
+                    size_t b;
+                    CHECK(align_up(want, b));
+                    size_t run = 0, best = 0;
+                    for (size_t u = 0; u < units; ++u) {
+                        run = used[u] ? 0 : run + 1;
+                        if (run > best) best = run;
+                    }
+                    CHECK(best * kAlign < b);
+                }
+            } else {
+                auto it = live.begin();
+                std::advance(it, (long)(rng() % live.size()));
+                size_t b;
+                CHECK(align_up(it->second, b));
+                for (size_t u = (it->first - base) / kAlign; u < (it->first - base + b) / kAlign; ++u) used[u] = 0;
+                A.release(it->first, it->second);
+                live.erase(it);
+            }
+            size_t nfree = 0;
+            for (char c : used) nfree += !c;
+            CHECK(A.free_bytes() == nfree * kAlign);
+            // free blocks never touch: they are merged on release
+            size_t prev_end = SIZE_MAX;
+            for (const auto &kv : A.blocks()) {
+                CHECK(kv.first != prev_end);
+                prev_end = kv.first + kv.second;
+            }
+        }
+        for (const auto &kv : live) A.release(kv.first, kv.second);
+        CHECK(A.blocks().size() == 1 && A.free_bytes() == units * kAlign);
+    }
+}
+
+static void admission(std::mt19937_64 &rng) {
+    for (int t = 0; t < 300; ++t) {
+        Arena A;
+        const size_t cap = (1 + rng() % 512) * kAlign;
+        A.init(0, cap);
+        const Caps caps{(int32_t)(1 + rng() % 8), (int64_t)(1 + rng() % 100000)};
+        std::map<uint64_t, Queued> reqs;
+        std::deque<uint64_t> q;
+        for (uint64_t id = 1; id <= 40; ++id) {
+            Queued r{(int64_t)(1 + rng() % 40000), (size_t)(1 + rng() % (cap / 2 + 1)), rng() % 7 == 0};
+            if (never_fits(r.n, r.bytes, caps, A)) continue;   // refused at submission
+            reqs[id] = r;
+            q.push_back(id);
+        }
+        int32_t slots = (int32_t)(rng() % 2);
+        int64_t resident = (int64_t)(rng() % 1000);
+        if (resident > caps.max_resident) resident = caps.max_resident;
+        const std::deque<uint64_t> before = q;
+        const int32_t s0 = slots;
+        const int64_t r0 = resident;
+        const auto got = admit_fcfs(q, [&](uint64_t id) { return reqs.at(id); }, caps, slots, resident, A);
+        // admitted requests are the non-cancelled ones of a prefix of the queue, in order
+        size_t k = 0, i = 0;
+        int64_t adds = 0;
+        for (; i < before.size() && k < got.size(); ++i) {
+            const Queued &r = reqs.at(before[i]);
+            if (r.cancelled) continue;
+            CHECK(got[k].first == before[i]);
+            adds += r.n;
+            ++k;
+        }
+        CHECK(k == got.size());
+        CHECK(slots == s0 + (int32_t)got.size() && resident == r0 + adds);
+        CHECK(slots <= caps.max_slots || got.empty());
+        CHECK(resident <= caps.max_resident || got.empty());
+        // the queue keeps the rest, starting at the first request that did not fit
+        while (i < before.size() && reqs.at(before[i]).cancelled) ++i;
+        if (!q.empty()) {
+            CHECK(q.front() == before[i]);
+            CHECK(!reqs.at(q.front()).cancelled);
+        }
+        // admitted blocks are disjoint
+        std::vector<std::pair<size_t, size_t>> blk;
+        for (const auto &g : got) blk.push_back({g.second, reqs.at(g.first).bytes});
+        for (size_t a = 0; a < blk.size(); ++a)
+            for (size_t b = a + 1; b < blk.size(); ++b) {
+                size_t ea, eb;
+                align_up(blk[a].second, ea);
+                align_up(blk[b].second, eb);
+                CHECK(blk[a].first + ea <= blk[b].first || blk[b].first + eb <= blk[a].first);
+            }
+    }
+    // a request of exactly the arena's capacity fits an empty arena; one byte more never does
+    Arena A;
+    A.init(4096, 10 * kAlign + 17);
+    const Caps caps{4, 1000};
+    CHECK(!never_fits(10, 10 * kAlign, caps, A));
+    CHECK(never_fits(10, 10 * kAlign + 1, caps, A));
+    CHECK(never_fits(1001, 256, caps, A));
+    std::map<uint64_t, Queued> reqs{{1, {10, 10 * kAlign, false}}};
+    std::deque<uint64_t> q{1};
+    int32_t slots = 0;
+    int64_t resident = 0;
+    const auto got = admit_fcfs(q, [&](uint64_t id) { return reqs.at(id); }, caps, slots, resident, A);
+    CHECK(got.size() == 1 && got[0].second == 4096 && q.empty());
+}
+
+int main() {
+    std::mt19937_64 rng(20260201);
+    layouts(rng);
+    list_layouts(rng);
+    arena(rng);
+    admission(rng);
+    if (failures) {
+        std::fprintf(stderr, "%d checks failed\n", failures);
+        return 1;
+    }
+    std::printf("all cases ok\n");
+    return 0;
+}

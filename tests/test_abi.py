@@ -112,3 +112,55 @@ def test_flag_combinations_accepted_on_the_host(bh, flags):
     p = bh.params(0.5, 0.01)
     p.flags = flags
     assert bh.lib().bh_workspace_bytes(1000, C.byref(p)) > 0
+
+
+# The boundary's required entry points and outputs: the calls the hot path exposes
+# (tree build, upward pass, forces, canonical export with node count and per-body
+# checksums, simulations, forests and the request API), the status codes and the
+# walk statistics with their time.
+REQUIRED = ["bh_ctx_create", "bh_ctx_destroy", "bh_ctx_sync", "bh_last_error", "bh_workspace_bytes", "bh_build",
+            "bh_upward", "bh_forces", "bh_forces_stats", "bh_tree_export", "bh_tree_free", "bh_sim_create",
+            "bh_step", "bh_energy", "bh_sim_destroy", "bh_forest_create", "bh_forest_step", "bh_forest_destroy",
+            "bh_server_create", "bh_server_submit", "bh_server_poll", "bh_server_fetch", "bh_server_cancel",
+            "bh_server_destroy", "bh_ic_generate", "bh_ic_workspace_bytes"]
+
+
+def _decl(name):
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    m = re.search(r"\b" + name + r"\s*\(([^;]*)\)\s*;", text, flags=re.S)
+    assert m, name
+    return " ".join(m.group(1).split())
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    assert not [n for n in REQUIRED if n not in names]
+    exp = _decl("bh_tree_export")
+    assert "int64_t *n_nodes" in exp and "uint64_t *isect_hash" in exp
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    stats = re.search(r"typedef struct \{([^}]*)\} bh_stats;", text, flags=re.S).group(1)
+    assert re.search(r"double t_ms;", stats)
+    for f in ("n_mono", "n_p2p", "n_visits", "n_fallback"):
+        assert f in stats
+    codes = dict(re.findall(r"(BH_E_[A-Z]+|BH_OK) = (\d+)", text))
+    assert codes == {"BH_OK": "0", "BH_E_INVAL": "1", "BH_E_NOMEM": "2", "BH_E_DEVICE": "3", "BH_E_BUSY": "4",
+                     "BH_E_NOTFOUND": "5", "BH_E_OVERFLOW": "6", "BH_E_CANCELLED": "7"}
+    # every device buffer comes from the caller: workspace arguments on the calls that need scratch
+    for name in ("bh_build", "bh_sim_create", "bh_forest_create", "bh_ic_generate"):
+        assert "void *ws" in _decl(name), name
+    assert "void *arena" in _decl("bh_server_create")
+
+
+def test_ic_workspace_size_without_gpu(bh):
+    L = bh.lib()
+    nb = L.bh_ic_workspace_bytes()
+    assert 256 < nb < 1 << 20 and nb % 256 == 0
+
+
+def test_library_makes_no_device_allocations():
+    """The library allocates no device memory of its own: no hipMalloc-family call in
+    its sources (all device buffers are carved from caller workspaces)."""
+    src = ROOT / "paper_1109_5190_amd" / "csrc"
+    for p in list(src.glob("*.hip")) + list(src.glob("*.h")):
+        text = re.sub(r"//[^\n]*", "", p.read_text())
+        assert not re.search(r"\bhip(Malloc|MallocAsync|ExtMallocWithFlags|HostMalloc|MallocManaged)\s*\(", text), p

@@ -50,6 +50,32 @@ def plummer_1m():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_plummer_1m_steps_reanchored(ctx, plummer_1m, prec):
+    """The headline run itself: 10 KDK steps of dt = 1e-4 at N = 2^20 with a rebuild every step,
+    as the benchmark times them.  At force evaluations 5 and 10 the oracle re-walks a tree built
+    from the GPU's own positions (re-anchored: trajectories need not agree bit for bit) on 1024
+    sampled targets: interaction sets equal, forces within the gates."""
+    s, _ = plummer_1m
+    p = bh.params(0.5, 0.005, precision=prec)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    sim = bh.Sim(ctx, pos, vel, mass, p)
+    rng = np.random.default_rng(55)
+    for ev in (5, 10):
+        print(f"[fullsize] plummer 2^20 {prec}: steps to evaluation {ev}", flush=True)
+        sim.step(5, 1e-4)
+        ctx.sync()
+        x = pos.cpu().numpy()
+        assert np.isfinite(x).all()
+        t = bh.Tree(ctx, pos, mass, p).upward()
+        r = t.forces_stats()
+        # the tree of the same positions gives the step's own accelerations bit for bit
+        assert torch.equal(r["acc"], sim.acc)
+        targets = np.sort(rng.choice(s.n, 1024, replace=False)).astype(np.int64)
+        sampled_check(oracle.Tree(x, s.mass, 1), r, targets, 0.5, 0.005, prec)
+        del t
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_plummer_1m_sampled(ctx, plummer_1m, prec):
     """Headline workload: N = 2^20, eps = 0.005, theta = 0.5, leaf_cap 1."""
     s, T = plummer_1m
