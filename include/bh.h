@@ -364,9 +364,24 @@ size_t bh_ic_workspace_bytes(void);
  * device outputs.  ws: caller-owned device workspace, 256-byte aligned, of
  * ws_bytes >= bh_ic_workspace_bytes() (BH_E_NOMEM otherwise).  SYNC: returns
  * BH_E_DEVICE if a velocity draw found no acceptance (the Plummer sampler
- * gives up after 401 rejection rounds; never seen in practice). */
+ * gives up after 401 rejection rounds and leaves the velocities non-finite;
+ * never seen in practice). */
 bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M,
                          double *pos, double *vel, double *mass, void *ws, size_t ws_bytes);
+
+/* bh_ic_generate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results bit for bit, with the generator's partial sums
+ * and fault word in a static array of the library (16 KiB per GPU, held until
+ * the process ends; the generator needs bh_ic_workspace_bytes() of it whatever
+ * n is, and the call returns BH_E_NOMEM should that ever exceed the array).
+ * Allocates nothing and does not synchronise: asynchronous on the context's
+ * stream.  A failed velocity draw is not reported; it leaves the velocities
+ * non-finite.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams or threads) race and must be ordered by
+ * the caller.  Same argument checks as bh_ic_generate (1 <= n <= 2^30 - 1). */
+bh_status bh_ic_generate_static(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M,
+                                double *pos, double *vel, double *mass);
 
 /* ---------------------------------------------------------------- serving --- */
 

@@ -100,6 +100,8 @@ _SIGS = {
     "bh_forest_energy": ([_VP, _VP, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_destroy": ([_VP, _VP], C.c_int),
     "bh_ic_workspace_bytes": ([], C.c_size_t),
+    "bh_ic_generate_static": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP],
+                              C.c_int),
     "bh_ic_generate": ([_VP, C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_double, _VP, _VP, _VP, _VP,
                         C.c_size_t], C.c_int),
     "bh_server_create": ([_VP, _VP, C.c_size_t, C.c_int32, C.c_int64, C.POINTER(_VP)], C.c_int),

@@ -3,6 +3,7 @@
 // context's stream and returns a bh_status; no exception crosses the ABI.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -311,6 +312,39 @@ struct EventPair {
 };
 }  // namespace
 
+// --------------------------------------------------------- static scratch ---
+// Device memory of the entry points that allocate nothing (bh_ic_generate_static):
+// one array per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol); it
+// uses the device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device when a context is created on it.
+constexpr size_t kStaticScratchBytes = 16384;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static bh_status static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return bh_fail(BH_E_INVAL, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return BH_OK;
+    void *ptr = nullptr;   // device `device` is current (the caller set it)
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return bh_fail(BH_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return BH_OK;
+}
+
+static void *static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 // ---------------------------------------------------------------- context ---
 
 extern "C" {
@@ -324,6 +358,8 @@ bh_status bh_ctx_create(int device, void *hip_stream, bh_ctx **out) {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return bh_fail(BH_E_INVAL, "no such device");
     HIPCHK(hipSetDevice(device));
+    bh_status sst = static_scratch_init(device);
+    if (sst != BH_OK) return sst;
     bh_ctx *c = new (std::nothrow) bh_ctx();
     if (!c) return bh_fail(BH_E_NOMEM, "host allocation failed");
     c->device = device;
@@ -851,6 +887,24 @@ bh_status bh_ic_generate(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, do
     HIPCHK(hipMemcpyAsync(&e, flag, sizeof(e), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (e) return bh_fail(BH_E_DEVICE, "initial conditions: a velocity draw found no acceptance in 401 tries");
+    return BH_OK;
+}
+
+bh_status bh_ic_generate_static(bh_ctx *ctx, int32_t kind, int64_t n, uint64_t seed, double a, double M,
+                                double *pos, double *vel, double *mass) {
+    if (!ctx || !pos || !vel || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (kind != 0 && kind != 1) return bh_fail(BH_E_INVAL, "kind must be 0 (Plummer) or 1 (cube)");
+    if (n < 1 || n > (int64_t)0x3fffffff) return bh_fail(BH_E_INVAL, "n out of range (1 .. 2^30 - 1)");
+    if (!(a > 0.0) || !(M > 0.0) || !std::isfinite(a) || !std::isfinite(M))
+        return bh_fail(BH_E_INVAL, "a and M must be positive and finite");
+    if (bh_ic_workspace_bytes() > kStaticScratchBytes)
+        return bh_fail(BH_E_NOMEM, "the generator's scratch exceeds the static array (" +
+                                       std::to_string(kStaticScratchBytes) + " bytes)");
+    char *base = static_cast<char *>(static_scratch(ctx->device));
+    if (!base) return bh_fail(BH_E_DEVICE, "no static scratch on this device (context not initialised)");
+    uint32_t *flag = reinterpret_cast<uint32_t *>(base + ic_flag_offset());
+    HIPCHK(launch_fill_u32(flag, 0, 1, ctx->stream));
+    HIPCHK(launch_ic(kind, n, seed, a, M, pos, vel, mass, reinterpret_cast<double *>(base), flag, ctx->stream));
     return BH_OK;
 }
 

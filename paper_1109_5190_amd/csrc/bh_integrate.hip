@@ -177,7 +177,10 @@ __global__ void k_ic(int kind, int64_t n, uint64_t seed, double a, double M, dou
                 draw2((uint64_t)i, call, kPlummerTag, seed, x4, x5);
                 if (0.1 * x5 < x4 * x4 * pow(1.0 - x4 * x4, 3.5)) { q = x4; ok = true; break; }
             }
-            if (!ok) atomicOr(err, kErrNonFinite);
+            if (!ok) {   // no acceptance: reported, and the velocities are left non-finite
+                atomicOr(err, kErrNonFinite);
+                q = NAN;
+            }
             const double sp = q * sqrt(2.0 * M / a) * pow(1.0 + r * r, -0.25);
             const double vz = (1.0 - 2.0 * x6) * sp;
             const double vr = sqrt(fmax(sp * sp - vz * vz, 0.0));
