@@ -932,17 +932,17 @@ __global__ void k_records(ForestDev f) {
         const float eps2f = (float)eps2;
         const bool eps_ok = eps2 == 0.0 || (eps2 > 1e-30 && eps2 < 1e30 && eps2f > 0.0f);
         if (sd.theta == 0.0) {
-            w.Sp = INFINITY;   // nothing is ever accepted
+            w.Sh = INFINITY;   // nothing is ever accepted
             w.band0 = 0.0f;
             w.band1 = 0.0f;
         } else {
             const double S = r2 / (sd.theta * sd.theta) + eps2;
             if (eps_ok && r2 > 1e-30 && S > 1e-30 && S < 1e30) {
-                w.Sp = (float)S;
+                w.Sh = (float)(S * (1.0 + 8.0 * u));   // the walk's band edges start from S (1 + 8u)
                 w.band0 = (float)(16.0 * u * S * (1.0 + 1e-6));
                 w.band1 = (float)(8.0 * u * sqrt(r2) / sd.theta * (1.0 + 1e-6));
             } else {
-                w.Sp = 0.0f;
+                w.Sh = 0.0f;
                 w.band0 = INFINITY;
                 w.band1 = 0.0f;
             }

@@ -64,7 +64,7 @@ struct GroupDesc { uint32_t start, count, seg, pad; };
 struct WRec32 {
     double cx, cy, cz;         // centre of mass (FP64)
     float m;                   // mass (FP32)
-    float Sp;                  // S = r^2 / theta^2 + eps^2 (FP32; +inf when theta = 0)
+    float Sh;                  // S (1 + 8u) of S = r^2 / theta^2 + eps^2, rounded (FP32; +inf when theta = 0)
     float band0;               // 16 u S (inf: S outside FP32 range, always decide in FP64)
     float band1;               // 8 u r / theta
     uint32_t link;             // internal: first child slot; leaf: first particle rank

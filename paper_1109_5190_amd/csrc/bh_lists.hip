@@ -44,7 +44,6 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
     rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
     const double theta = sd.theta;
     const float eps2 = (float)(sd.eps * sd.eps);
-    const float band2 = 16.0f * kU32 * kU32;
 
     uint32_t ne = 0, total = 0, prev = kListNone;   // wave-uniform
     unsigned long long res = 0;                      // next reserved local chunk index
@@ -98,10 +97,8 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
             const float qx = (float)__dsub_rn(w.cx, gx);
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
-            const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
-            const float B = fmaf(rho, fmaf(band2, rho, w.band1), w.band0);
             L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            L.sb[lane] = make_float2((w.Sp + B) * (1.0f + 4.0f * kU32), fmaxf(w.Sp - B, 0.0f) * (1.0f - 4.0f * kU32));
+            L.sb[lane] = open_band(w, qx, qy, qz, rw);
             L.sl[lane] = make_uint2(w.link, w.cnt);
             L.sc[lane] = make_uint2(w.gid, w.level);
         }
@@ -202,7 +199,7 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
             if (POT) ap -= mr;
         }
     };
-    auto flush_leaves = [&]() {
+    auto pair_batch = [&]() {
         if (qn == 0) return;
         if (work + qn > kFlushWork) fold();
         work += qn;
@@ -266,6 +263,29 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
         wave_sync();
     };
 
+    // the walk's leaf pairs: after each stack entry, the queued particles, then the
+    // leaves that did not fit the queue
+    uint32_t nov = 0;
+    auto flush = [&]() {
+        pair_batch();
+        for (uint32_t j = 0; j < nov; ++j) {
+            const uint4 lf = L.ovf[j];
+            const uint32_t first = uni(lf.x), np = uni(lf.y);
+            const uint64_t m = ((uint64_t)uni(lf.w) << 32) | uni(lf.z);
+            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    L.irank[lane] = first + b0 + lane;
+                    L.imask[lane] = m;
+                }
+                qn = nb;
+                pair_batch();
+            }
+        }
+        nov = 0;
+    };
+
     const uint32_t n = uni(ld.count[gi]);
     uint32_t chunk = uni(ld.head[gi]);
     for (uint32_t k0 = 0; k0 < n; k0 += 64) {
@@ -285,28 +305,22 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
             const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.w, k) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.z, k);
             if (a == kListEntry) {
+                if (qn > 56u || nov) flush();   // the previous entry's pairs
                 if (work + b > kFlushWork) fold();
                 work += b;
             } else if (b & kListLeaf) {
                 const uint32_t np = b & ~kListLeaf;
-                if (np <= 64u) {
-                    if (qn + np > 64u) flush_leaves();
+                if (qn + np <= 64u) {
+                    wave_sync();
                     if ((uint32_t)lane < np) {
                         L.irank[qn + lane] = a + lane;
                         L.imask[qn + lane] = m;
                     }
                     qn += np;
                 } else {
-                    flush_leaves();
-                    for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                        const uint32_t nq = np - b0 < 64u ? np - b0 : 64u;
-                        if ((uint32_t)lane < nq) {
-                            L.irank[lane] = a + b0 + lane;
-                            L.imask[lane] = m;
-                        }
-                        qn = nq;
-                        flush_leaves();
-                    }
+                    wave_sync();
+                    if (lane == 0) L.ovf[nov] = make_uint4(a, np, (uint32_t)m, (uint32_t)(m >> 32));
+                    ++nov;
                 }
             } else if (in_mask(m)) {
                 const float4 qa = mst[k];
@@ -363,7 +377,7 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
         }
         chunk = uni(ld.next[chunk]);
     }
-    flush_leaves();
+    flush();
     fold();
     if (live) {
         const uint32_t i = f.idx[r];

@@ -47,7 +47,6 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
     const double theta = sd.theta;
     const float eps2 = (float)(sd.eps * sd.eps);
-    const float band2 = 16.0f * kU32 * kU32;   // 16 u^2
     constexpr bool soft = SOFT;
 
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
@@ -80,7 +79,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     };
     // queued leaf particles: load and convert lane-parallel, then one pass per particle
     uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
-    auto flush_leaves = [&]() {
+    auto pair_batch = [&]() {
         if (qn == 0) return;
         if (STATS) wwork += qn;
         if (work + qn > kFlushWork) fold();
@@ -155,30 +154,65 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
         qn = 0;
         wave_sync();
     };
+    // Leaf pairs are taken at one point after each stack entry: the queued particles
+    // in queue order, then the leaves that did not fit (64 particles at a time).
+    uint32_t nov = 0;   // leaves in L.ovf (wave-uniform)
+    auto flush = [&]() {
+        pair_batch();
+        for (uint32_t k = 0; k < nov; ++k) {
+            const uint4 lf = L.ovf[k];
+            const uint32_t first = uni(lf.x), np = uni(lf.y);
+            const uint64_t m = ((uint64_t)uni(lf.w) << 32) | uni(lf.z);
+            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    L.irank[lane] = first + b0 + lane;
+                    L.imask[lane] = m;
+                }
+                qn = nb;
+                pair_batch();
+            }
+        }
+        nov = 0;
+    };
 
+    // Depth-first stack of (first child slot, children, lane mask); the most recent
+    // push stays in scalar registers and is the next pop, so only entries pushed
+    // beneath another one go through LDS.
     int sp = 0;
-    const uint64_t m0 = ballot(live);
-    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
-    wave_sync();
-    sp = 1;
-    while (sp > 0) {
-        --sp;
-        const uint4 e = L.stk[sp];
-        const uint32_t link = uni(e.x), nch = uni(e.y);
+    bool pend = true;
+    uint32_t p_link = sid, p_cnt = 1u;
+    uint64_t p_mask = ballot(live);
+    const size_t lane_off = (size_t)lane;
+    for (;;) {
+        uint32_t link, nch;
+        uint64_t emask;
+        if (pend) {
+            link = p_link;
+            nch = p_cnt;
+            emask = p_mask;
+            pend = false;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            const uint4 e = L.stk[sp];
+            link = uni(e.x);
+            nch = uni(e.y);
+            emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+        }
         if (STATS) wwork += nch;
-        const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
         if ((uint32_t)lane < nch) {
-            const WRec32 &w = f.w32[link + lane];
+            const WRec32 *wb = f.w32 + link;   // wave-uniform base, lane offset
+            const WRec32 &w = wb[lane_off];
             const float qx = (float)__dsub_rn(w.cx, gx);
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
-            const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
-            const float B = fmaf(rho, fmaf(band2, rho, w.band1), w.band0);
             L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            L.sb[lane] = make_float2((w.Sp + B) * (1.0f + 4.0f * kU32), fmaxf(w.Sp - B, 0.0f) * (1.0f - 4.0f * kU32));
+            L.sb[lane] = open_band(w, qx, qy, qz, rw);
             L.sl[lane] = make_uint2(w.link, w.cnt);
-            L.sc[lane] = make_uint2(w.gid, w.level);
+            if (STATS) L.sc[lane] = make_uint2(w.gid, w.level);
             if (QUAD) {
                 L.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
                 L.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
@@ -219,34 +253,33 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                     const uint2 ql = L.sl[c];
                     const uint32_t qlink = uni(ql.x), qcnt = uni(ql.y);
                     if (qcnt & kLeafBit) {
+                        // queued; its pairs are taken after this entry
                         const uint32_t np = qcnt & ~kLeafBit;
                         if (STATS) ++wleaf;
-                        if (np <= 64u) {
-                            if (qn + np > 64u) flush_leaves();
+                        if (qn + np <= 64u) {
                             if ((uint32_t)lane < np) {
                                 L.irank[qn + lane] = qlink + lane;
                                 L.imask[qn + lane] = open;
                             }
                             qn += np;
                         } else {
-                            // a leaf of more than 64 particles (coincident particles at the depth limit)
-                            flush_leaves();
-                            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                                if ((uint32_t)lane < nb) {
-                                    L.irank[lane] = qlink + b0 + lane;
-                                    L.imask[lane] = open;
-                                }
-                                qn = nb;
-                                flush_leaves();
+                            if (lane == 0) L.ovf[nov] = make_uint4(qlink, np, (uint32_t)open, (uint32_t)(open >> 32));
+                            ++nov;
+                        }
+                    } else {
+                        if (pend) {   // the pending entry goes beneath the new one
+                            if (sp < kStackMax) {
+                                if (lane == 0)
+                                    L.stk[sp] = make_uint4(p_link, p_cnt, (uint32_t)p_mask, (uint32_t)(p_mask >> 32));
+                                ++sp;
+                            } else if (lane == 0) {
+                                atomicOr(f.err, kErrStack);   // result void; the walk still drains
                             }
                         }
-                    } else if (sp < kStackMax) {
-                        if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
-                        wave_sync();
-                        ++sp;
-                    } else if (lane == 0) {
-                        atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                        pend = true;
+                        p_link = qlink;
+                        p_cnt = qcnt;
+                        p_mask = open;
                     }
                 }
             }
@@ -312,8 +345,10 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                 }
             }
         }
+        // room for the next entry's eight children: at most 56 queued particles, no overflow
+        if (qn > 56u || nov) flush();
     }
-    flush_leaves();
+    flush();
     fold();
     const bool own = live && r >= out.wlo && r < out.whi;
     if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;

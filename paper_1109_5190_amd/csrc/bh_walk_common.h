@@ -94,7 +94,21 @@ struct WaveLds32 {
     uint64_t imask[64];    //                        lane mask
     float4 pst[64];        //                        position rel g, mass (unsoftened walks:
                            //                        32 particles as (hi, mass), (lo, 0))
+    uint4 ovf[8];          // opened leaves that did not fit the queue: first rank, count, mask
 };
+
+// Opening thresholds of a child for one wavefront (FP32 walks): E2 > hi accepts,
+// E2 < lo opens, anything between is decided in FP64.  q: the child's centre
+// relative to the wavefront's reference g; rw: bound of |x - g|_inf over its bodies.
+// With rho >= |q|_inf + rw and B = band0 + rho (band1 + 16 u^2 rho) the record's
+// Sh >= S (1 + 6u) gives hi >= S + B and Sh (1 - 20u) - B (1 + 4u) <= S - B (lo
+// rounds to a negative value, which never opens, when B exceeds it); B = inf
+// (thresholds outside the FP32 range) sends every lane to FP64.
+__device__ __forceinline__ float2 open_band(const WRec32 &w, float qx, float qy, float qz, float rw) {
+    const float rho = fmaf(fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz))), 1.0f + 4.0f * kU32, rw);
+    const float B = fmaf(rho, fmaf(16.0f * kU32 * kU32, rho, w.band1), w.band0);
+    return make_float2(fmaf(B, 1.0f + 4.0f * kU32, w.Sh), fmaf(B, -(1.0f + 4.0f * kU32), w.Sh * (1.0f - 20.0f * kU32)));
+}
 
 
 template <bool QUAD>
