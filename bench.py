@@ -138,7 +138,7 @@ def sweep(a, bh, torch):
             quad, group = variant == "quadrupole", variant == "group"
             open_ = variant if variant in ("bmax", "offset") else "side"
             if group:
-                ref = T.walk_group(theta, 0.005, 1.0, 64, tg, nthreads=cores)
+                ref = T.walk_group(theta, 0.005, 1.0, 64, tg, nthreads=cores, starts=T.group_cubes(64))
             else:
                 ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores, quad=quad, open=open_)
             inter = None
@@ -188,7 +188,7 @@ def sweep(a, bh, torch):
                                    "2^22 in [-1,1]^3, masses U[0.5,1.5]/N, seed 5; eps 0.005; leaf_cap "
                                    f"{a.leaf_cap}; per-body monopole at theta 0.3-1.0; at 0.5-1.0 the quadrupole, "
                                    "the b_max and centre-offset opening radii, and the group criterion "
-                                   "(64-body groups)",
+                                   "(groups: largest cubes of at most 64 bodies)",
                        "error_sample": f"{a.sample} random targets per system (against the oracle at the same "
                                        "settings, and against direct summation)"},
             "results": rows}

@@ -82,12 +82,15 @@ typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
  *              - (3 S.d - tr S d) / s^5]).  The paper names multipole moments as future
  *              work (section 6).  Interaction sets are unchanged.
  *            BH_GROUP_CRITERION: a variant of the opening test (not the paper's): the
- *              bodies of a walk group (64 key-consecutive bodies) share one decision per
- *              cube, accepted iff side^2 < theta^2 D^2 with D the distance from the
- *              cube's centre of mass to the group's bounding box; opened leaves give pairs
- *              with every particle but the body itself.  More conservative (and more
- *              accurate) than the per-body test; all lanes of a wavefront take part in
- *              every cube.  Not combined with BH_QUADRUPOLE.
+ *              bodies of a group share one decision per cube, accepted iff
+ *              side^2 < theta^2 D^2 with D the distance from the cube's centre of mass
+ *              to the group's bounding box (FP64, as the per-body test); opened leaves
+ *              give pairs with every particle but the body itself.  A body's group is
+ *              the largest cube of the tree holding at most 64 bodies (a leaf of more
+ *              than 64 coincident bodies is cut into runs of 64 in key order), so a
+ *              group never spans cubes that a larger cube separates.  More
+ *              conservative (and more accurate) than the per-body test.  Not combined
+ *              with BH_QUADRUPOLE.
  *            BH_OPEN_BMAX: alternative opening radius (section 6 names other ways of
  *              computing the criterion as future work): accept iff r^2 < theta^2 D^2
  *              with r = b_max, the largest distance from the cube's centre of mass to

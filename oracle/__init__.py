@@ -62,6 +62,11 @@ def lib():
         L.or_tree_moments.argtypes = [C.c_void_p, _f64p]
         L.or_tree_walk_group.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_int64, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.or_tree_walk_group_ranges.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, _i64p, C.c_int64,
+                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p, C.c_int]
+        L.or_tree_group_cubes.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        L.or_tree_group_cubes.restype = C.c_int64
         L.or_tree_export.argtypes = [C.c_void_p, _f64p, C.POINTER(C.c_int32), _u64p, _u32p, _i32p,
                                      _u32p, _u32p, _i32p, _i32p, _f64p, _f64p]
         opt = lambda t: C.c_void_p  # noqa: E731  (nullable array arguments)
@@ -184,8 +189,18 @@ class Tree:
             raise ValueError("oracle walk rejected its arguments")
         return dict(acc=acc, pot=pot, n_mono=nm, n_p2p=np_, hash=hs)
 
-    def walk_group(self, theta=0.5, eps=0.01, G=1.0, group=64, targets=None, nthreads=0):
-        """Group-criterion variant: one interaction list per `group` key-consecutive bodies."""
+    def group_cubes(self, cap=64):
+        """Start ranks of the cube-based groups (largest cubes holding at most cap bodies), n at the end."""
+        ng = lib().or_tree_group_cubes(self._h, int(cap), None)
+        if ng < 1:
+            raise ValueError("bad group cap")
+        starts = np.zeros(ng + 1, np.int64)
+        lib().or_tree_group_cubes(self._h, int(cap), starts.ctypes.data_as(C.c_void_p))
+        return starts
+
+    def walk_group(self, theta=0.5, eps=0.01, G=1.0, group=64, targets=None, nthreads=0, starts=None):
+        """Group-criterion variant: one interaction list per group of key-consecutive bodies,
+        `group` at a time, or the groups given by their start ranks (`starts`, n at the end)."""
         p = params(theta, eps, G, 1)
         t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
         nt = self.n if t is None else t.shape[0]
@@ -194,8 +209,13 @@ class Tree:
         nm = np.zeros(nt, np.int64)
         np_ = np.zeros(nt, np.int64)
         hs = np.zeros(nt, np.uint64)
-        rc = lib().or_tree_walk_group(self._h, C.byref(p), int(group), nt, _ptr(t), _ptr(acc), _ptr(pot),
-                                      _ptr(nm), _ptr(np_), _ptr(hs), int(nthreads))
+        if starts is None:
+            rc = lib().or_tree_walk_group(self._h, C.byref(p), int(group), nt, _ptr(t), _ptr(acc), _ptr(pot),
+                                          _ptr(nm), _ptr(np_), _ptr(hs), int(nthreads))
+        else:
+            st = np.ascontiguousarray(starts, dtype=np.int64)
+            rc = lib().or_tree_walk_group_ranges(self._h, C.byref(p), st.shape[0] - 1, st, nt, _ptr(t), _ptr(acc),
+                                                 _ptr(pot), _ptr(nm), _ptr(np_), _ptr(hs), int(nthreads))
         if rc:
             raise ValueError("oracle group walk rejected its arguments")
         return dict(acc=acc, pot=pot, n_mono=nm, n_p2p=np_, hash=hs)

@@ -431,6 +431,9 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
 }
 
 /* ---- group-criterion walk: one interaction list per group of key-consecutive bodies ---- */
+int or_tree_walk_group_ranges(const or_tree *t, const or_params *p, int64_t ngroups, const int64_t *starts,
+                              int64_t ntarget, const int64_t *targets, double *acc, double *pot,
+                              int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, int nthreads);
 typedef struct { int32_t *id; int64_t n, cap; } id_list;
 
 static void list_push(id_list *l, int32_t v)
@@ -442,18 +445,63 @@ static void list_push(id_list *l, int32_t v)
     l->id[l->n++] = v;
 }
 
+/* ---- the groups of the group criterion: largest cubes holding at most cap bodies ----
+ * In depth-first preorder the cubes whose parent holds more than cap bodies (or the
+ * root) and which hold at most cap bodies partition the key order into consecutive
+ * runs; a leaf of more than cap bodies (coincident bodies at the depth limit) is cut
+ * into runs of cap. */
+int64_t or_tree_group_cubes(const or_tree *t, int32_t cap, int64_t *starts)
+{
+    if (!t || cap < 1) return -1;
+    int64_t ng = 0;
+    for (int64_t id = 0; id < t->nn; id++) {
+        const uint32_t c = t->count[id];
+        const int32_t par = t->parent[id];
+        const int top = par < 0 || t->count[par] > (uint32_t)cap;
+        if (!top) continue;
+        if (c <= (uint32_t)cap) {
+            if (starts) starts[ng] = t->first[id];
+            ng++;
+        } else if (t->nchild[id] == 0) {
+            for (uint32_t r = 0; r < c; r += (uint32_t)cap) {
+                if (starts) starts[ng] = (int64_t)t->first[id] + r;
+                ng++;
+            }
+        }
+    }
+    if (starts) starts[ng] = t->n;
+    return ng;
+}
+
 int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int64_t ntarget,
                        const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, int nthreads)
 {
-    if (!t || !p || group < 1 || !(p->theta >= 0.0) || !(p->eps >= 0.0)) return 1;
+    if (!t || group < 1) return 1;
+    const int64_t ng = (t->n + group - 1) / group;
+    int64_t *starts = (int64_t *)malloc(sizeof(int64_t) * (ng + 1));
+    for (int64_t g = 0; g < ng; g++) starts[g] = g * group;
+    starts[ng] = t->n;
+    int rc = or_tree_walk_group_ranges(t, p, ng, starts, ntarget, targets, acc, pot, n_mono, n_p2p, hash,
+                                       nthreads);
+    free(starts);
+    return rc;
+}
+
+int or_tree_walk_group_ranges(const or_tree *t, const or_params *p, int64_t ngroups, const int64_t *starts,
+                              int64_t ntarget, const int64_t *targets, double *acc, double *pot,
+                              int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, int nthreads)
+{
+    if (!t || !p || ngroups < 1 || !starts || !(p->theta >= 0.0) || !(p->eps >= 0.0)) return 1;
     if (p->open != OR_OPEN_SIDE) return 1;   /* the group test is defined with the side only */
+    if (starts[0] != 0 || starts[ngroups] != t->n) return 1;
+    for (int64_t g = 0; g < ngroups; g++)
+        if (starts[g + 1] <= starts[g]) return 1;
     const int64_t n = t->n;
     double *A = (double *)malloc(sizeof(double) * 3 * n), *P = (double *)malloc(sizeof(double) * n);
     int64_t *NM = (int64_t *)malloc(sizeof(int64_t) * n), *NP = (int64_t *)malloc(sizeof(int64_t) * n);
     uint64_t *H = (uint64_t *)malloc(sizeof(uint64_t) * n);
     const double theta2 = p->theta * p->theta, eps2 = p->eps * p->eps, L = ldexp(1.0, t->k);
-    const int64_t ngroups = (n + group - 1) / group;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -461,7 +509,7 @@ int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int6
 #endif
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ngroups; g++) {
-        const int64_t r0 = g * group, r1 = r0 + group < n ? r0 + group : n;
+        const int64_t r0 = starts[g], r1 = starts[g + 1];
         double lo[3], hi[3];
         for (int k = 0; k < 3; k++) lo[k] = hi[k] = t->spos[3 * r0 + k];
         for (int64_t r = r0 + 1; r < r1; r++)

@@ -103,8 +103,10 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
                  const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
                  int64_t *n_p2p, uint64_t *hash, int nthreads);
 
-/* Group-criterion walk (a variant, not the paper's per-body test): the bodies in
- * key order are split into consecutive groups of `group` (the last one shorter);
+/* Group-criterion walk (a variant, not the paper's per-body test) over fixed-size
+ * groups: the bodies in key order are split into consecutive groups of `group` (the
+ * last one shorter); the library's groups are the cube groups of or_tree_group_cubes,
+ * walked by or_tree_walk_group_ranges;
  * a cube is accepted for a whole group iff side^2 < theta^2 D^2 with D the distance
  * from the cube's centre of mass to the group's bounding box (0 inside it), in
  * FP64 as ((dx*dx + dy*dy) + dz*dz) with dk = max(0, lo_k - c_k, c_k - hi_k).
@@ -113,6 +115,17 @@ int or_tree_walk(const or_tree *t, const double *pos, const or_params *p, int64_
 int or_tree_walk_group(const or_tree *t, const or_params *p, int32_t group, int64_t ntarget,
                        const int64_t *targets, double *acc, double *pot, int64_t *n_mono,
                        int64_t *n_p2p, uint64_t *hash, int nthreads);
+
+/* The same walk over explicit groups: group g holds the bodies of sorted ranks
+ * [starts[g], starts[g + 1]), starts[0] = 0, starts[ngroups] = n, increasing. */
+int or_tree_walk_group_ranges(const or_tree *t, const or_params *p, int64_t ngroups, const int64_t *starts,
+                              int64_t ntarget, const int64_t *targets, double *acc, double *pot,
+                              int64_t *n_mono, int64_t *n_p2p, uint64_t *hash, int nthreads);
+
+/* Groups of the cube-based group criterion: the largest cubes holding at most cap
+ * bodies, in key order (a leaf of more than cap bodies is cut into runs of cap).
+ * Writes starts[0..ng] (nullable: count only) and returns ng (-1 on bad input). */
+int64_t or_tree_group_cubes(const or_tree *t, int32_t cap, int64_t *starts);
 
 /* build + walk in one call */
 int or_forces(int64_t n, const double *pos, const double *mass, const or_params *p,

@@ -76,7 +76,7 @@ void bh_forest_tables(ForestHost &F, int32_t nseg, const int64_t *n, const bh_pa
         d.quad = (p[s].flags & BH_QUADRUPOLE) ? 1u : 0u;
         d.group = (p[s].flags & BH_GROUP_CRITERION) ? 1u : 0u;
         d.open = (p[s].flags & BH_OPEN_BMAX) ? kOpenBmax : (p[s].flags & BH_OPEN_OFFSET) ? kOpenOffset : kOpenSide;
-        (p[s].precision == BH_FP32 ? has32 : has64) |= d.group ? kVarGroup : var_bit(d.quad != 0, unsoftened(d.eps));
+        (p[s].precision == BH_FP32 ? has32 : has64) |= var_bit(d.quad != 0, unsoftened(d.eps), d.group != 0);
         for (uint32_t t = 0; t < d.ntiles; ++t) {
             uint32_t st = d.start + t * kTile;
             uint32_t c = (uint32_t)std::min<int64_t>(kTile, n[s] - (int64_t)t * kTile);
@@ -109,6 +109,7 @@ ForestCaps bh_caps_of(const ForestHost &F) {
     c.fp32 = F.dev.has32 != 0;
     c.fp64 = F.dev.has64 != 0;
     c.quad = ((F.dev.has32 | F.dev.has64) & kVarQuadBits) != 0;
+    c.group = ((F.dev.has32 | F.dev.has64) & kVarGroupBits) != 0;
     return c;
 }
 
@@ -168,6 +169,7 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
         {(void **)&D.stats, 8, 8},
         {(void **)&D.red, 2 * S, 8},
         {(void **)&D.pot, N, 8},
+        {(void **)&D.gbox, cap.group ? 6 * N : 0, 8},
     };
     std::vector<bh_host::Region> regions;
     for (const Slot &sl : slots) regions.push_back(bh_host::Region{sl.count, sl.elem});
@@ -206,7 +208,8 @@ bh_status bh_forest_upload_tables(ForestHost &F) {
     ForestDev &D = F.dev;
     const ForestCaps &c = F.caps;
     if (D.nseg > c.nseg || D.ntot > c.ntot || D.ntiles > c.ntiles || D.ngroups > c.ngroups ||
-        (D.has32 && !c.fp32) || (D.has64 && !c.fp64) || (((D.has32 | D.has64) & kVarQuadBits) && !c.quad))
+        (D.has32 && !c.fp32) || (D.has64 && !c.fp64) || (((D.has32 | D.has64) & kVarQuadBits) && !c.quad) ||
+        (((D.has32 | D.has64) & kVarGroupBits) && !c.group))
         return bh_fail(BH_E_NOMEM, "forest membership exceeds the planned capacity");
     HIPCHK(hipMemcpyAsync(D.seg, F.seg.data(), sizeof(SegDesc) * F.seg.size(), hipMemcpyHostToDevice, s));
     if (!F.tiles.empty())

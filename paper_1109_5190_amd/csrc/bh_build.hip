@@ -976,8 +976,42 @@ __global__ void k_records(ForestDev f) {
     }
 }
 
+// Group criterion: each body's group is the largest cube holding at most kGroupCap
+// bodies (its parent holds more, or it is the root); a leaf of more than kGroupCap
+// coincident bodies at the depth limit is cut into runs of kGroupCap in key order.
+// One thread per group cube writes the group's bounding box (FP64 min and max of
+// its bodies' coordinates) to each member's row.
+__global__ void __launch_bounds__(256) k_group_boxes(ForestDev f) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mtot = f.base[f.ntot];
+    if (g >= mtot) return;
+    const uint32_t first = f.nfirst[g], cnt = f.ncount[g];
+    if (first >= f.ntot || cnt == 0 || cnt > f.ntot - first) return;   // flagged by the build
+    if (!f.seg[f.segid[first]].group) return;
+    const uint32_t par = f.nparent[g];
+    const bool top = par == kNone || (par < mtot && f.ncount[par] > (uint32_t)kGroupCap);
+    if (!top || (cnt > (uint32_t)kGroupCap && f.nchild[g] != 0)) return;
+    for (uint32_t r0 = first; r0 < first + cnt; r0 += kGroupCap) {
+        const uint32_t r1 = r0 + kGroupCap < first + cnt ? r0 + kGroupCap : first + cnt;
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) lo[d] = hi[d] = f.spos[3 * (size_t)r0 + d];
+        for (uint32_t r = r0 + 1; r < r1; ++r)
+            for (int d = 0; d < 3; ++d) {
+                const double v = f.spos[3 * (size_t)r + d];
+                lo[d] = v < lo[d] ? v : lo[d];
+                hi[d] = v > hi[d] ? v : hi[d];
+            }
+        for (uint32_t r = r0; r < r1; ++r)
+            for (int d = 0; d < 3; ++d) {
+                f.gbox[6 * (size_t)r + d] = lo[d];
+                f.gbox[6 * (size_t)r + 3 + d] = hi[d];
+            }
+    }
+}
+
 hipError_t launch_upward(const ForestDev &f, hipStream_t s) {
     const unsigned mb = (f.mcap + 255) / 256;
+    if (f.gbox) hipLaunchKernelGGL(k_group_boxes, dim3(mb), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_up_leaf, dim3(mb), dim3(256), 0, s, f);
     // one wavefront per list block; the lists cover the node ids [0, mcap) in blocks of 256
     const unsigned nblk = mb;

@@ -35,7 +35,7 @@ struct SegDesc {
     double *vel, *acc, *pot;
     uint32_t phase;             // kPhase* bits: which parts of a step apply this iteration
     uint32_t quad;              // 1: accepted cubes add their quadrupole term
-    uint32_t group;             // 1: group criterion (a cube is accepted for the whole walk group)
+    uint32_t group;             // 1: group criterion (a cube is accepted for all bodies of a group cube)
     uint32_t open;              // kOpen*: opening radius r of the test r^2 < theta^2 D^2
 };
 
@@ -123,6 +123,7 @@ struct ForestDev {
     unsigned long long *stats;  // 4 totals (n_mono, n_p2p, n_visits, n_fallback)
     double *red;                // reduction scratch (energy)
     double *pot;                // potential scratch (ntot)
+    double *gbox;               // group criterion, per sorted row: its group's bounding box lo[3], hi[3]
 };
 
 // ---------------------------------------------------------------- helpers ---
@@ -133,14 +134,16 @@ __device__ __forceinline__ void flag_tree(const ForestDev &f) {
     atomicOr(f.err + kErrWordTree, kErrTree);
 }
 
-// Walk variant of a simulation: expansion order and whether its FP32 softening is zero
-// (one bit each of ForestDev::has32 / has64; the FP64 walk ignores the softening bit).
-constexpr uint32_t kVarQuad = 1u, kVarUnsoft = 2u;
-__host__ __device__ __forceinline__ uint32_t var_bit(bool quad, bool unsoft) {
-    return 1u << ((quad ? kVarQuad : 0u) | (unsoft ? kVarUnsoft : 0u));
+// Walk variant of a simulation: expansion order, whether its FP32 softening is zero and
+// whether it uses the group criterion (one bit each of ForestDev::has32 / has64; the
+// FP64 walk ignores the softening bit; the quadrupole is not combined with groups).
+constexpr uint32_t kVarQuad = 1u, kVarUnsoft = 2u, kVarGroup = 4u;
+__host__ __device__ __forceinline__ uint32_t var_bit(bool quad, bool unsoft, bool group = false) {
+    return 1u << ((quad ? kVarQuad : 0u) | (unsoft ? kVarUnsoft : 0u) | (group ? kVarGroup : 0u));
 }
 constexpr uint32_t kVarQuadBits = (1u << kVarQuad) | (1u << (kVarQuad | kVarUnsoft));
-constexpr uint32_t kVarGroup = 1u << 4;   // group-criterion simulations (their own walk kernels)
+constexpr uint32_t kVarGroupBits = (1u << kVarGroup) | (1u << (kVarGroup | kVarUnsoft));
+constexpr int kGroupCap = 64;   // group criterion: a group is a largest cube of at most this many bodies
 
 // A simulation's FP32 walk is unsoftened when eps^2 rounds to zero in FP32.
 __host__ __device__ __forceinline__ bool unsoftened(double eps) { return !((float)(eps * eps) > 0.0f); }

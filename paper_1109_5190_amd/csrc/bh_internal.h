@@ -18,6 +18,7 @@ struct ForestCaps {
     uint32_t nseg = 0, ntot = 0, ntiles = 0, ngroups = 0;
     bool fp32 = false, fp64 = false;
     bool quad = false;   // second-moment buffers for quadrupole simulations
+    bool group = false;  // group boxes for group-criterion simulations
 };
 
 struct ForestHost {

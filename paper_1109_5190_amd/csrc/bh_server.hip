@@ -266,6 +266,7 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     cap.ngroups = (uint32_t)(max_resident_particles / kGroup + max_slots + 1);
     cap.fp32 = cap.fp64 = true;
     cap.quad = true;
+    cap.group = true;
     size_t ws = bh_forest_carve(sv->F, cap, nullptr);
     const size_t scratch_bytes = align256(ic_scratch_bytes());
     if (ws == 0 || ws + scratch_bytes >= arena_bytes) {

@@ -35,7 +35,6 @@ hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *ac
     if (f.ngroups == 0) return hipSuccess;
     launch_walk32_family(f, o, stats, want_pot, waves, s);
     launch_walk64_family(f, o, stats, want_pot, waves, s);
-    launch_gwalk_family(f, o, stats, want_pot, s);
     return hipGetLastError();
 }
 

@@ -21,7 +21,12 @@ namespace bh {
 // repeat the test in FP64 exactly as the oracle evaluates it.  Pair terms go
 // into FP32 partial sums that are folded into Kahan-compensated totals after
 // at most 64 terms.
-template <bool STATS, bool POT, int W, bool QUAD, bool SOFT>
+//
+// GROUP (the group-criterion variant): each lane decides with its group's
+// bounding box instead of its own position, in FP64 as the oracle writes it
+// (group_accepts), so the FP32 band is not used; pair and monopole terms are the
+// per-body walk's.
+template <bool STATS, bool POT, int W, bool QUAD, bool SOFT, bool GROUP>
 __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     __shared__ WaveLds32 lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -32,7 +37,8 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 1 || sd.group || (sd.quad != 0) != QUAD || unsoftened(sd.eps) == SOFT) return;
+    if (sd.precision != 1 || (sd.group != 0) != GROUP || (sd.quad != 0) != QUAD || unsoftened(sd.eps) == SOFT)
+        return;
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
@@ -46,6 +52,13 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
     for (int o = 32; o > 0; o >>= 1) rw = fmaxf(rw, __shfl_xor(rw, o, 64));
     rw = __uint_as_float(uni(__float_as_uint(rw))) * (1.0f + 4.0f * kU32);
     const double theta = sd.theta;
+    double blo[3], bhi[3];   // GROUP: this lane's group box
+    if (GROUP)
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = f.gbox[6 * (size_t)r + d];
+            bhi[d] = f.gbox[6 * (size_t)r + 3 + d];
+        }
+    const double theta2 = __dmul_rn(theta, theta);
     const float eps2 = (float)(sd.eps * sd.eps);
     constexpr bool soft = SOFT;
 
@@ -210,12 +223,19 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
             L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            L.sb[lane] = open_band(w, qx, qy, qz, rw);
+            if (GROUP) {
+                L.x.g.cx[lane] = w.cx;
+                L.x.g.cy[lane] = w.cy;
+                L.x.g.cz[lane] = w.cz;
+                L.x.g.r2[lane] = w.r2;
+            } else {
+                L.sb[lane] = open_band(w, qx, qy, qz, rw);
+            }
             L.sl[lane] = make_uint2(w.link, w.cnt);
             if (STATS) L.sc[lane] = make_uint2(w.gid, w.level);
             if (QUAD) {
-                L.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
-                L.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
+                L.x.q.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
+                L.x.q.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
             }
         }
         wave_sync();
@@ -228,10 +248,16 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
             const float4 qa = L.sa[c];
             const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
             const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-            uint64_t accm = ballot(E2 > L.sb[c].x) & emask;
-            uint64_t open = emask & ~accm;
+            uint64_t accm, open;
+            if (GROUP) {
+                accm = ballot(group_accepts(L.x.g.cx[c], L.x.g.cy[c], L.x.g.cz[c], L.x.g.r2[c], blo, bhi, theta2)) &
+                       emask;
+            } else {
+                accm = ballot(E2 > L.sb[c].x) & emask;
+            }
+            open = emask & ~accm;
             if (open) {
-                const uint64_t ambm = ballot(!(E2 < L.sb[c].y)) & open;
+                const uint64_t ambm = GROUP ? 0 : ballot(!(E2 < L.sb[c].y)) & open;
                 if (ambm) {
                     // within the FP32 rounding bound of the threshold: decide exactly in FP64
                     bool ex = false;
@@ -296,7 +322,7 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
                 float w3 = mr * ri2;
                 if (QUAD) {
                     // + G [5 A d / (2 s^7) - (3 S.d - tr S d) / s^5],  A = 3 d.S.d - s^2 tr S
-                    const float4 s0 = L.sq0[c], s1 = L.sq1[c];
+                    const float4 s0 = L.x.q.sq0[c], s1 = L.x.q.sq1[c];
                     const float sdx = fmaf(s0.x, dx, fmaf(s0.w, dy, s1.x * dz));
                     const float sdy = fmaf(s0.w, dx, fmaf(s0.y, dy, s1.y * dz));
                     const float sdz = fmaf(s1.x, dx, fmaf(s1.y, dy, s0.z * dz));
@@ -396,10 +422,14 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
 template <bool STATS, bool POT, int W>
 static void launch_w32(const ForestDev &f, const WalkOut &o, hipStream_t s) {
     const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
-    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, true>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, true, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, false, false>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, false, true))
+        hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true, true>), g, b, 0, s, f, o);
+    if (f.has32 & var_bit(false, true, true))
+        hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false, true>), g, b, 0, s, f, o);
 }
 
 template <bool POT>
@@ -413,7 +443,7 @@ static void launch_w32_shape(const ForestDev &f, const WalkOut &o, int W, hipStr
 }
 
 void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
-    if (!(f.has32 & ~kVarGroup)) return;
+    if (!f.has32) return;
     if (stats) {   // the counting walks use one launch shape
         if (pot) launch_w32<true, true, 4>(f, o, s);
         else launch_w32<true, false, 4>(f, o, s);

@@ -6,7 +6,9 @@ namespace bh {
 // ------------------------------------------------------------- FP64 walk ---
 
 
-template <bool STATS, bool POT, int W, bool QUAD>
+// GROUP (the group-criterion variant): each lane tests cubes against its group's
+// bounding box (group_accepts) instead of its own position.
+template <bool STATS, bool POT, int W, bool QUAD, bool GROUP>
 __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     __shared__ WaveLds64<QUAD> lds_all[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -17,13 +19,19 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
-    if (sd.precision != 0 || sd.group || (sd.quad != 0) != QUAD) return;
+    if (sd.precision != 0 || (sd.group != 0) != GROUP || (sd.quad != 0) != QUAD) return;
     const SegState &st = f.st[sid];
     const uint32_t gstart = uni(gd.start);
     const bool live = (uint32_t)lane < gd.count;
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
     const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
     const double theta2 = __dmul_rn(sd.theta, sd.theta);
+    double blo[3], bhi[3];   // GROUP: this lane's group box
+    if (GROUP)
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = f.gbox[6 * (size_t)r + d];
+            bhi[d] = f.gbox[6 * (size_t)r + 3 + d];
+        }
     const double eps2 = __dmul_rn(sd.eps, sd.eps);
     const bool soft = eps2 > 0.0;
 
@@ -101,7 +109,8 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
             const double S = L.sS[c];
             const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
             const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            const uint64_t accm = ballot(S < __dmul_rn(theta2, D2)) & emask;
+            const uint64_t accm =
+                ballot(GROUP ? group_accepts(qa.x, qa.y, qa.z, S, blo, bhi, theta2) : S < __dmul_rn(theta2, D2)) & emask;
             if (STATS && in_mask(emask)) ++nvis;
             const uint64_t open = emask & ~accm;
             if (open) {
@@ -212,8 +221,9 @@ template <bool STATS, bool POT, int W>
 static void launch_w64(const ForestDev &f, const WalkOut &o, hipStream_t s) {
     const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
     if (f.has64 & (var_bit(false, false) | var_bit(false, true)))
-        hipLaunchKernelGGL((k_walk64<STATS, POT, W, false>), g, b, 0, s, f, o);
-    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true>), g, b, 0, s, f, o);
+        hipLaunchKernelGGL((k_walk64<STATS, POT, W, false, false>), g, b, 0, s, f, o);
+    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true, false>), g, b, 0, s, f, o);
+    if (f.has64 & kVarGroupBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, false, true>), g, b, 0, s, f, o);
 }
 
 template <bool POT>
@@ -227,7 +237,7 @@ static void launch_w64_shape(const ForestDev &f, const WalkOut &o, int W, hipStr
 }
 
 void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
-    if (!(f.has64 & ~kVarGroup)) return;
+    if (!f.has64) return;
     if (stats) {   // the counting walks use one launch shape
         if (pot) launch_w64<true, true, 4>(f, o, s);
         else launch_w64<true, false, 4>(f, o, s);

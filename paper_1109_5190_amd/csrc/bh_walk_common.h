@@ -89,7 +89,14 @@ struct WaveLds32 {
     float2 sb[8];          // child: accept above hi, decide in FP64 at or above lo (this wavefront)
     uint2 sl[8];           // child: link, cnt
     uint2 sc[8];           // child: gid, level
-    float4 sq0[8], sq1[8]; // child (quadrupole walks): second moments (xx yy zz xy) (xz yz tr 0)
+    union {
+        struct {
+            float4 sq0[8], sq1[8];             // second moments (xx yy zz xy) (xz yz tr 0)
+        } q;                                   // child, quadrupole walks
+        struct {
+            double cx[8], cy[8], cz[8], r2[8]; // FP64 centre of mass, r^2 of the test
+        } g;                                   // child, group-criterion walks
+    } x;
     uint32_t irank[64];    // queued leaf particles: rank
     uint64_t imask[64];    //                        lane mask
     float4 pst[64];        //                        position rel g, mass (unsoftened walks:
@@ -123,11 +130,28 @@ struct WaveLds64 {
     double4 pst[32];            //                        position, mass (32 at a time)
 };
 
+// Group criterion (a variant, not the paper's per-body test): the cube is accepted
+// for every body of a group iff r^2 < theta^2 D^2, D the distance from the cube's
+// centre of mass c to the group's bounding box [lo, hi] (0 inside it), evaluated
+// in FP64 exactly as the oracle writes it.
+__device__ __forceinline__ bool group_accepts(double cx, double cy, double cz, double r2, const double lo[3],
+                                              const double hi[3], double theta2) {
+    const double c[3] = {cx, cy, cz};
+    double dd[3];
+    for (int k = 0; k < 3; ++k) {
+        const double u = __dsub_rn(lo[k], c[k]), v = __dsub_rn(c[k], hi[k]);
+        const double w = u > v ? u : v;
+        dd[k] = w > 0.0 ? w : 0.0;
+    }
+    const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dd[0], dd[0]), __dmul_rn(dd[1], dd[1])), __dmul_rn(dd[2], dd[2]));
+    return r2 < __dmul_rn(theta2, D2);
+}
+
 // Launchers of one kernel family each (defined in their own translation unit):
 // W wavefronts (one 64-body walk group each) per workgroup; stats: the counting
-// variant (totals, per-body counts and checksums); pot: also the potential.
+// variant (totals, per-body counts and checksums); pot: also the potential.  Each
+// launches the variants (expansion order, softening, opening test) its forest holds.
 void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s);
 void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s);
-void launch_gwalk_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, hipStream_t s);
 
 }  // namespace bh

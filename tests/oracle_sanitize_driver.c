@@ -95,9 +95,17 @@ static int run_case(int64_t n, int kind, int32_t leaf_cap) {
                     /* unsoftened walks of coincident bodies are singular by definition */
                     if (b == 0 && !finite_all(acc, 3 * n)) bad |= fail("walk output", n, kind);
                     if (open == OR_OPEN_SIDE && !quad) {
-                        for (int32_t g = 1; g <= 64; g *= 8)
+                        for (int32_t g = 1; g <= 64; g *= 8) {
                             if (or_tree_walk_group(t, &p, g, n, NULL, acc, pot, nm, np, hash, 1) != 0)
                                 bad |= fail("or_tree_walk_group", n, kind);
+                            /* the cube groups of at most g bodies */
+                            const int64_t ng = or_tree_group_cubes(t, g, NULL);
+                            int64_t *starts = malloc(sizeof(int64_t) * (ng > 0 ? ng + 1 : 1));
+                            if (ng < 1 || or_tree_group_cubes(t, g, starts) != ng ||
+                                or_tree_walk_group_ranges(t, &p, ng, starts, n, NULL, acc, pot, nm, np, hash, 1) != 0)
+                                bad |= fail("or_tree_group_cubes / walk_group_ranges", n, kind);
+                            free(starts);
+                        }
                     }
                 }
     }

@@ -122,7 +122,7 @@ def test_export_node_count_and_checksums(ctx, prec, group):
     ctx.sync()
     T = oracle.Tree(s.pos, s.mass, 1)
     assert ex["n_nodes"] == T.nn
-    ref = T.walk_group(0.6, 0.01, 1.0, 64) if group else T.walk(0.6, 0.01)
+    ref = T.walk_group(0.6, 0.01, 1.0, starts=T.group_cubes(64)) if group else T.walk(0.6, 0.01)
     assert np.array_equal(u64(ex["isect_hash"]), ref["hash"])
     assert torch.equal(ex["isect_hash"], st["hash"])
 

@@ -183,7 +183,7 @@ def test_plummer_1m_variants_sampled(ctx, plummer_1m, variant):
     rng = np.random.default_rng(14)
     targets = np.sort(rng.choice(s.n, 1024, replace=False)).astype(np.int64)
     if variant == "group":
-        ref = T.walk_group(0.5, 0.005, 1.0, 64, targets, nthreads=CORES)
+        ref = T.walk_group(0.5, 0.005, 1.0, 64, targets, nthreads=CORES, starts=T.group_cubes(64))
     else:
         ref = T.walk(0.5, 0.005, 1.0, targets, nthreads=CORES, quad=variant == "quadrupole",
                      open=variant if variant in ("bmax", "offset") else "side")

@@ -1,5 +1,6 @@
-"""GPU parity of the group-criterion variant (BH_GROUP_CRITERION) against the oracle's
-group walk: interaction sets equal, forces within the FP64 (1e-10 RMS) and FP32
+"""GPU parity of the group-criterion variant (BH_GROUP_CRITERION: groups are the
+largest cubes of at most 64 bodies) against the oracle's group walk over the same
+cube groups: interaction sets equal, forces within the FP64 (1e-10 RMS) and FP32
 (2e-6 RMS, 1e-4 max) gates; forests mixing the two criteria equal each simulation
 alone."""
 import numpy as np
@@ -40,7 +41,7 @@ def make(kind, n, seed):
 CASES = [
     ("plummer", 4096, 1, 0.5, 0.01, 1),
     ("plummer", 4096, 1, 1.0, 0.01, 8),
-    ("cube", 10001, 5, 0.6, 0.005, 1),        # ragged last group
+    ("cube", 10001, 5, 0.6, 0.005, 1),        # ragged last walk window
     ("plummer", 20000, 4, 0.8, 0.0, 1),       # unsoftened pairs
     ("two_spheres", 20000, 3, 0.5, 0.005, 2),
     ("duplicates", 5000, 7, 0.6, 0.01, 2),    # a leaf of 1250 coincident bodies
@@ -53,7 +54,7 @@ def test_group_walk_parity(ctx, prec, kind, n, seed, theta, eps, cap):
     print(f"[group] {kind} n={n} theta={theta} eps={eps} leaf_cap={cap} {prec}", flush=True)
     s = make(kind, n, seed)
     T = oracle.Tree(s.pos, s.mass, cap)
-    ref = T.walk_group(theta, eps, 1.0, group=64)
+    ref = T.walk_group(theta, eps, 1.0, starts=T.group_cubes(64))
     t = bh.Tree(ctx, dev(s.pos), dev(s.mass), bh.params(theta, eps, leaf_cap=cap, precision=prec, group=True)).upward()
     r = t.forces_stats(pot=True)
     assert torch.equal(t.forces(), r["acc"])
