@@ -81,20 +81,35 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
         wave_sync();
     };
 
+    // Depth-first stack of (first child slot, children, lane mask); the most recent
+    // push stays in scalar registers and is the next pop, so only entries pushed
+    // beneath another one go through LDS.
     int sp = 0;
-    const uint64_t m0 = ballot(live);
-    if (lane == 0) L.stk[0] = make_uint4(sid, 1u, (uint32_t)m0, (uint32_t)(m0 >> 32));
-    wave_sync();
-    sp = 1;
-    while (sp > 0) {
-        --sp;
-        const uint4 e = L.stk[sp];
-        const uint32_t link = uni(e.x), nch = uni(e.y);
+    bool pend = true;
+    uint32_t p_link = sid, p_cnt = 1u;
+    uint64_t p_mask = ballot(live);
+    const size_t lane_off = (size_t)lane;
+    for (;;) {
+        uint32_t link, nch;
+        uint64_t emask;
+        if (pend) {
+            link = p_link;
+            nch = p_cnt;
+            emask = p_mask;
+            pend = false;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            const uint4 e = L.stk[sp];
+            link = uni(e.x);
+            nch = uni(e.y);
+            emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+        }
         if (STATS) wwork += nch;
-        const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
         if ((uint32_t)lane < nch) {
-            const WRec64 &w = f.w64[link + lane];
+            const WRec64 *wb = f.w64 + link;   // wave-uniform base, lane offset
+            const WRec64 &w = wb[lane_off];
             L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
             L.sS[lane] = w.S;
             L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
@@ -137,12 +152,20 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
                             flush_leaves();
                         }
                     }
-                } else if (sp < kStackMax) {
-                    if (lane == 0) L.stk[sp] = make_uint4(qlink, qcnt, (uint32_t)open, (uint32_t)(open >> 32));
-                    wave_sync();
-                    ++sp;
-                } else if (lane == 0) {
-                    atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                } else {
+                    if (pend) {   // the pending entry goes beneath the new one
+                        if (sp < kStackMax) {
+                            if (lane == 0)
+                                L.stk[sp] = make_uint4(p_link, p_cnt, (uint32_t)p_mask, (uint32_t)(p_mask >> 32));
+                            ++sp;
+                        } else if (lane == 0) {
+                            atomicOr(f.err, kErrStack);   // result void; the walk still drains
+                        }
+                    }
+                    pend = true;
+                    p_link = qlink;
+                    p_cnt = qcnt;
+                    p_mask = open;
                 }
             }
             if (in_mask(accm)) {
