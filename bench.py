@@ -216,7 +216,7 @@ def batch(a, bh, torch):
     vel = torch.tensor(cat.vel, device=dev)
     mass = torch.tensor(cat.mass, device=dev)
     forest = bh.Forest(ctx, ns, plist, pos, vel, mass)
-    waves, tune_ms = forest.autotune()
+    shape, tune_ms = forest.autotune()
     acc0 = forest.acc.cpu().numpy()
     dts = [1e-3] * len(ns)
     forest.step_graph(1, dts)      # records the graph and warms up
@@ -249,7 +249,9 @@ def batch(a, bh, torch):
             "config": {"workload": "512 Plummer instances, N log-uniform in [1024, 262144] (seed 6), theta from "
                                    "{0.4, 0.5, 0.7}, eps 0.01, dt 1e-3, KDK with a rebuild every step",
                        "total_particles": total, "leaf_cap": a.leaf_cap},
-            "autotune": {"walk_waves_per_workgroup": waves, "walk_ms_by_waves": tune_ms},
+            "autotune": {"walk_shape": bh.shape_name(shape),
+                         "walk_ms_by_shape": {bh.shape_name(k): v for k, v in tune_ms.items()},
+                         "shapes": "wavefronts per workgroup; p: persistent form (work queue)"},
             "force_error_vs_oracle": {"rms_rel": rms, "max_rel": mx,
                                       "sample": "256 targets on each of 8 instances stratified by N, initial positions"}}
 

@@ -59,7 +59,8 @@ typedef enum {
     BH_E_BUSY = 4,       /* request not finished yet */
     BH_E_NOTFOUND = 5,   /* unknown request id */
     BH_E_OVERFLOW = 6,   /* walk stack overflow (cannot happen for depth <= 21; reported if it does) */
-    BH_E_CANCELLED = 7   /* request was cancelled */
+    BH_E_CANCELLED = 7,  /* request was cancelled */
+    BH_E_IO = 8          /* a tuning-cache file could not be read, parsed or written */
 } bh_status;
 
 typedef enum { BH_FP64 = 0, BH_FP32 = 1 } bh_precision;
@@ -339,15 +340,49 @@ bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *f, double *pot);
 /* Record one step of the forest as a HIP graph (on first call) and replay it
  * nsteps times. */
 bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *f, int32_t nsteps, const double *dt);
+/* Walk launch shapes (the load-balancing analogue of the paper's work queues and
+ * grain size, sections 3 and 5).  A shape is the number of wavefronts per
+ * workgroup, 1, 2, 4 or 8 (each wavefront walks one 64-body group at a time),
+ * optionally or'ed with BH_WALK_PERSISTENT: then the launch has only as many
+ * workgroups as the device holds at once and each wavefront takes the next group
+ * from a counter in the workspace until none is left.  The shape changes no
+ * result; it decides how the uneven per-group work meets the compute units.
+ * Trees, simulations and forests start with shape 4. */
+#define BH_WALK_PERSISTENT 0x100
+#define BH_TUNE_SHAPES 8   /* 1, 2, 4, 8, then 1, 2, 4, 8 | BH_WALK_PERSISTENT */
+bh_status bh_tree_set_walk_shape(bh_ctx *ctx, bh_tree *tree, int32_t shape);
+bh_status bh_sim_set_walk_shape(bh_ctx *ctx, bh_sim *sim, int32_t shape);
+/* A recorded step graph is re-recorded at its next replay when the shape changes. */
+bh_status bh_forest_set_walk_shape(bh_ctx *ctx, bh_forest *f, int32_t shape);
 /* SYNC.  Autotuner of the forest's walk launch shape: builds the tree at the
- * current positions, times the force walk (two launches after a warm-up, HIP
- * events on the context's stream) with 1, 2, 4 and 8 wavefronts per workgroup
- * (one 64-body group per wavefront) and keeps the fastest for this forest's
- * later evaluations; a recorded step graph is re-recorded.  The shape changes
- * no result.  waves_out (nullable): the chosen count; ms_out (nullable, host
- * array of 4): measured walk times in ms in the order 1, 2, 4, 8.  acc is
- * refreshed as a side effect (forces at the current positions). */
-bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *f, int32_t *waves_out, double *ms_out);
+ * current positions and times the force walk (two launches after a warm-up, HIP
+ * events on the context's stream) in each of the BH_TUNE_SHAPES shapes, keeps the
+ * fastest for this forest's later evaluations (a recorded step graph is
+ * re-recorded) and stores it in the process's tuning cache under the forest's key:
+ * device (architecture and compute units), floor(log2 total bodies),
+ * floor(log2 simulations), theta (body-weighted mean, to 0.01) and precision mix.
+ * flags: BH_TUNE_CACHED takes the cached shape for that key without timing when
+ * there is one.  shape_out (nullable): the chosen shape; ms_out (nullable, host
+ * array of BH_TUNE_SHAPES): measured walk times in ms in the order above, all -1
+ * when the shape came from the cache.  acc is refreshed as a side effect (forces
+ * at the current positions).  With the environment variable BH_TUNE_CACHE naming
+ * a file, the first autotuner call of the process merges that file into the cache
+ * (a missing file is an empty cache) and every timed call writes the cache back. */
+#define BH_TUNE_CACHED 1u
+bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *f, uint32_t flags, int32_t *shape_out, double *ms_out);
+/* The process's tuning cache as JSON text:
+ *   {"format": "bh-tune-cache", "version": 1, "entries": [{"device": "gfx950:256",
+ *    "n_log2": 20, "sims_log2": 0, "theta": 0.5, "precision": "fp32", "shape": 4,
+ *    "ms": 2.77}, ...]}
+ * load merges a file's entries (equal keys replaced; all or nothing: BH_E_IO with
+ * the reason in bh_last_error on a missing file or any syntax or schema error);
+ * save writes every entry (BH_E_IO when the file cannot be written); clear empties
+ * the cache.  Thread-safe; the cache is shared by all contexts of the process. */
+bh_status bh_tune_cache_load(const char *path);
+bh_status bh_tune_cache_save(const char *path);
+bh_status bh_tune_cache_clear(void);
+/* Number of entries in the tuning cache. */
+int64_t bh_tune_cache_size(void);
 /* SYNC.  Per-simulation energies at the current positions: out_KW[2 s] = K_s,
  * out_KW[2 s + 1] = W_s (host array of 2 n_sims); also refreshes acc. */
 bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *f, double *out_KW);

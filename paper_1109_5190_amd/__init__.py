@@ -16,7 +16,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "libbh.so"
 
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_OVERFLOW, E_CANCELLED = range(8)
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_OVERFLOW, E_CANCELLED, E_IO = range(9)
 FP64, FP32 = 0, 1
 
 
@@ -36,6 +36,16 @@ GROUP_CRITERION = 4
 OPEN_BMAX = 8
 OPEN_OFFSET = 16
 OPEN = {"side": 0, "bmax": OPEN_BMAX, "offset": OPEN_OFFSET}
+
+WALK_PERSISTENT = 0x100
+TUNE_CACHED = 1
+# the autotuner's shapes, in the order of its timings: wavefronts per workgroup, grid then persistent form
+TUNE_SHAPES = (1, 2, 4, 8, 1 | WALK_PERSISTENT, 2 | WALK_PERSISTENT, 4 | WALK_PERSISTENT, 8 | WALK_PERSISTENT)
+
+
+def shape_name(shape):
+    """'4' for four wavefronts per workgroup, '4p' for the persistent form."""
+    return f"{shape & 0xff}{'p' if shape & WALK_PERSISTENT else ''}"
 
 
 def params(theta=0.5, eps=0.01, G=1.0, leaf_cap=1, precision="fp64", quad=False, group=False,
@@ -96,7 +106,14 @@ _SIGS = {
     "bh_forest_step": ([_VP, _VP, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_forces": ([_VP, _VP, _VP], C.c_int),
     "bh_forest_step_graph": ([_VP, _VP, C.c_int32, C.POINTER(C.c_double)], C.c_int),
-    "bh_forest_autotune": ([_VP, _VP, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
+    "bh_forest_autotune": ([_VP, _VP, C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
+    "bh_tree_set_walk_shape": ([_VP, _VP, C.c_int32], C.c_int),
+    "bh_sim_set_walk_shape": ([_VP, _VP, C.c_int32], C.c_int),
+    "bh_forest_set_walk_shape": ([_VP, _VP, C.c_int32], C.c_int),
+    "bh_tune_cache_load": ([C.c_char_p], C.c_int),
+    "bh_tune_cache_save": ([C.c_char_p], C.c_int),
+    "bh_tune_cache_clear": ([], C.c_int),
+    "bh_tune_cache_size": ([], C.c_int64),
     "bh_forest_energy": ([_VP, _VP, C.POINTER(C.c_double)], C.c_int),
     "bh_forest_destroy": ([_VP, _VP], C.c_int),
     "bh_ic_workspace_bytes": ([], C.c_size_t),
@@ -306,6 +323,11 @@ class Tree:
         _check(lib().bh_shard_bounds_groups(self.ctx.h, self.h, _ptr(group_work), int(G), _ptr(b)))
         return b
 
+    def set_walk_shape(self, shape):
+        """Wavefronts per workgroup (1, 2, 4, 8), | WALK_PERSISTENT for the persistent form."""
+        _check(lib().bh_tree_set_walk_shape(self.ctx.h, self.h, int(shape)))
+        return self
+
     def info(self):
         nn = C.c_int64()
         lo = (C.c_double * 3)()
@@ -373,6 +395,9 @@ class Sim:
     def step(self, nsteps, dt):
         _check(lib().bh_step(self.ctx.h, self.h, int(nsteps), float(dt)))
 
+    def set_walk_shape(self, shape):
+        _check(lib().bh_sim_set_walk_shape(self.ctx.h, self.h, int(shape)))
+
     def energy(self):
         kw = (C.c_double * 2)()
         _check(lib().bh_energy(self.ctx.h, self.h, kw))
@@ -427,13 +452,17 @@ class Forest:
     def step_graph(self, nsteps, dt):
         _check(lib().bh_forest_step_graph(self.ctx.h, self.h, int(nsteps), self._dt(dt)))
 
-    def autotune(self):
-        """Times the walk with 1, 2, 4 and 8 wavefronts per workgroup at the current
-        positions and keeps the fastest.  Returns (waves, {waves: ms})."""
+    def autotune(self, cached=False):
+        """Times the walk in every launch shape (TUNE_SHAPES) at the current positions and keeps
+        the fastest; cached: take the tuning cache's shape for this forest's key when it has one
+        (timings then -1).  Returns (shape, {shape: ms})."""
         w = C.c_int32()
-        ms = (C.c_double * 4)()
-        _check(lib().bh_forest_autotune(self.ctx.h, self.h, C.byref(w), ms))
-        return int(w.value), {k: float(ms[i]) for i, k in enumerate((1, 2, 4, 8))}
+        ms = (C.c_double * len(TUNE_SHAPES))()
+        _check(lib().bh_forest_autotune(self.ctx.h, self.h, TUNE_CACHED if cached else 0, C.byref(w), ms))
+        return int(w.value), {k: float(ms[i]) for i, k in enumerate(TUNE_SHAPES)}
+
+    def set_walk_shape(self, shape):
+        _check(lib().bh_forest_set_walk_shape(self.ctx.h, self.h, int(shape)))
 
     def forces(self, pot=None):
         _check(lib().bh_forest_forces(self.ctx.h, self.h, _ptr(pot)))
@@ -528,3 +557,20 @@ def ic_generate(ctx: Context, kind, n, seed, a=1.0, M=1.0):
     _check(lib().bh_ic_generate(ctx.h, int(kind), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, float(a), float(M),
                                 _ptr(pos), _ptr(vel), _ptr(mass), _ptr(ws), nb))
     return pos, vel, mass
+
+
+def tune_cache_load(path):
+    """bh_tune_cache_load: merges the JSON tuning cache at `path` into the process's cache."""
+    _check(lib().bh_tune_cache_load(str(path).encode()))
+
+
+def tune_cache_save(path):
+    _check(lib().bh_tune_cache_save(str(path).encode()))
+
+
+def tune_cache_clear():
+    _check(lib().bh_tune_cache_clear())
+
+
+def tune_cache_size():
+    return int(lib().bh_tune_cache_size())

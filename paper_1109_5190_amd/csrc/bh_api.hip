@@ -1,7 +1,10 @@
 // C ABI of libbh.so: contexts, workspace planning, trees, simulations and
 // forests.  Every entry point validates its arguments, enqueues kernels on the
 // context's stream and returns a bh_status; no exception crosses the ABI.
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -170,6 +173,7 @@ size_t bh_forest_carve(ForestHost &F, const ForestCaps &cap, char *ws) {
         {(void **)&D.red, 2 * S, 8},
         {(void **)&D.pot, N, 8},
         {(void **)&D.gbox, cap.group ? 6 * N : 0, 8},
+        {(void **)&D.wq, kWalkQueues, 4},
     };
     std::vector<bh_host::Region> regions;
     for (const Slot &sl : slots) regions.push_back(bh_host::Region{sl.count, sl.elem});
@@ -249,7 +253,7 @@ bh_status bh_forest_eval(ForestHost &F, const double *pos, const double *mass, d
     if (!s) s = F.ctx->stream;
     HIPCHK(launch_build(F.dev, pos, mass, s));
     HIPCHK(launch_upward(F.dev, s));
-    HIPCHK(launch_walk(F.dev, false, want_pot, acc, pot, nullptr, nullptr, nullptr, s, F.walk_waves));
+    HIPCHK(launch_walk(F.dev, false, want_pot, acc, pot, nullptr, nullptr, nullptr, s, F.walk_shape));
     return BH_OK;
 }
 
@@ -522,7 +526,7 @@ bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces");
     HIPCHK(launch_walk(t->F.dev, false, pot != nullptr, acc, pot, nullptr, nullptr, nullptr, ctx->stream,
-                       t->F.walk_waves));
+                       t->F.walk_shape));
     return BH_OK;
 }
 
@@ -536,7 +540,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
     HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
     HIPCHK(hipEventRecord(ev.a, ctx->stream));
     HIPCHK(launch_walk(t->F.dev, true, pot != nullptr, acc, pot, n_mono, n_p2p, hash, ctx->stream,
-                       t->F.walk_waves));
+                       t->F.walk_shape));
     HIPCHK(hipEventRecord(ev.b, ctx->stream));
     unsigned long long h[8];
     HIPCHK(hipMemcpyAsync(h, t->F.dev.stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
@@ -575,7 +579,7 @@ bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count,
     if (stats) HIPCHK(launch_fill_u32((uint32_t *)t->F.dev.stats, 0, 16, ctx->stream));
     // a part of the groups loses less to the launch's tail with one wavefront per workgroup
     // (the whole tree keeps its own shape); the shape changes no result
-    const int waves = count == n ? t->F.walk_waves : 1;
+    const int waves = count == n ? t->F.walk_shape : 1;
     HIPCHK(launch_walk(D, stats, pot != nullptr, acc, pot, n_mono, n_p2p, nullptr, ctx->stream, waves,
                        (uint32_t)first, (uint32_t)(first + count), work, group_work));
     return BH_OK;
@@ -620,7 +624,7 @@ bh_status bh_tree_export(bh_ctx *ctx, bh_tree *t, uint64_t *keys, uint32_t *perm
     HIPCHK(launch_export(t->F.dev, 0, keys, perm, level, first, count, parent, M, com, ctx->stream));
     if (isect_hash)   // the counting walk, writing only the per-body checksums
         HIPCHK(launch_walk(t->F.dev, true, false, nullptr, nullptr, nullptr, nullptr, isect_hash, ctx->stream,
-                           t->F.walk_waves));
+                           t->F.walk_shape));
     if (n_nodes || isect_hash) {
         SegState st;
         HIPCHK(hipMemcpyAsync(&st, t->F.dev.st, sizeof(SegState), hipMemcpyDeviceToHost, ctx->stream));
@@ -802,46 +806,202 @@ bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const
 }
 
 
-bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, int32_t *waves_out, double *ms_out) {
+// ------------------------------------------------------------- autotuner ---
+
+static std::mutex g_tune_mu;
+static bh_host::TuneCache g_tune;
+static bool g_tune_env_read = false;
+
+static bool valid_walk_shape(int32_t shape) { return bh_host::valid_shape(shape); }
+
+static int tune_shape(int k) { return kWalkWaves[k & 3] | (k >= 4 ? kWalkPersistent : 0); }
+
+// The key a forest's tuned shape is kept under.
+static bh_host::TuneKey tune_key(const ForestHost &F) {
+    bh_host::TuneKey k;
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, F.ctx->device) == hipSuccess) {
+        std::string arch(pr.gcnArchName);
+        k.device = arch.substr(0, arch.find(':')) + ":" + std::to_string(pr.multiProcessorCount);
+    } else {
+        k.device = "device" + std::to_string(F.ctx->device);
+    }
+    k.n_log2 = bh_host::floor_log2(F.dev.ntot);
+    k.sims_log2 = bh_host::floor_log2(F.dev.nseg);
+    double wt = 0.0, tot = 0.0;
+    for (const SegDesc &d : F.seg) {
+        wt += (double)d.n * d.theta;
+        tot += (double)d.n;
+    }
+    const double th = tot > 0.0 ? wt / tot : 0.0;
+    k.theta_c = (int)std::lround(std::min(th, 1.0e4) * 100.0);
+    k.precision = F.dev.has32 && F.dev.has64 ? "mixed" : F.dev.has32 ? "fp32" : "fp64";
+    return k;
+}
+
+static bool read_file(const char *path, std::string &out) {
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return false;
+    char buf[4096];
+    size_t r;
+    out.clear();
+    while ((r = std::fread(buf, 1, sizeof buf, fp)) > 0) {
+        out.append(buf, r);
+        if (out.size() > (64u << 20)) {   // no tuning cache is this large
+            std::fclose(fp);
+            return false;
+        }
+    }
+    const bool ok = !std::ferror(fp);
+    std::fclose(fp);
+    return ok;
+}
+
+// Caller holds g_tune_mu.
+static bh_status tune_load_locked(const char *path, bool missing_ok) {
+    std::string text, err;
+    if (!read_file(path, text)) {
+        if (missing_ok) {
+            FILE *fp = std::fopen(path, "rb");
+            if (!fp) return BH_OK;   // no file yet: an empty cache
+            std::fclose(fp);
+        }
+        return bh_fail(BH_E_IO, std::string("cannot read tuning cache ") + path);
+    }
+    if (!g_tune.merge_json(text, err)) return bh_fail(BH_E_IO, std::string("tuning cache ") + path + ": " + err);
+    return BH_OK;
+}
+
+static bh_status tune_save_locked(const char *path) {
+    const std::string text = g_tune.to_json();
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return bh_fail(BH_E_IO, std::string("cannot write tuning cache ") + path);
+    const bool ok = std::fwrite(text.data(), 1, text.size(), fp) == text.size();
+    if (std::fclose(fp) != 0 || !ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return bh_fail(BH_E_IO, std::string("cannot write tuning cache ") + path);
+    }
+    return BH_OK;
+}
+
+bh_status bh_tune_cache_load(const char *path) {
+    if (!path) return bh_fail(BH_E_INVAL, "NULL path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return tune_load_locked(path, false);
+}
+
+bh_status bh_tune_cache_save(const char *path) {
+    if (!path) return bh_fail(BH_E_INVAL, "NULL path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return tune_save_locked(path);
+}
+
+bh_status bh_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return BH_OK;
+}
+
+int64_t bh_tune_cache_size(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int64_t)g_tune.size();
+}
+
+static void forest_take_shape(bh_forest *fo, int shape) {
+    if (shape != fo->F.walk_shape) {
+        fo->F.walk_shape = shape;
+        if (fo->graph) {   // recorded with the previous launch shape
+            (void)hipGraphExecDestroy(fo->graph);
+            fo->graph = nullptr;
+        }
+    }
+}
+
+bh_status bh_tree_set_walk_shape(bh_ctx *ctx, bh_tree *t, int32_t shape) {
+    if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
+    t->F.walk_shape = shape;
+    return BH_OK;
+}
+
+bh_status bh_sim_set_walk_shape(bh_ctx *ctx, bh_sim *sm, int32_t shape) {
+    if (!ctx || !sm) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
+    sm->F.walk_shape = shape;
+    return BH_OK;
+}
+
+bh_status bh_forest_set_walk_shape(bh_ctx *ctx, bh_forest *fo, int32_t shape) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
+    forest_take_shape(fo, shape);
+    return BH_OK;
+}
+
+bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, uint32_t flags, int32_t *shape_out, double *ms_out) {
+    if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (flags & ~BH_TUNE_CACHED) return bh_fail(BH_E_INVAL, "unknown bits in flags");
     hipStream_t s = ctx->stream;
     ForestHost &F = fo->F;
+    const char *env = std::getenv("BH_TUNE_CACHE");
+    const bh_host::TuneKey key = tune_key(F);
+    bh_host::TuneEntry hit;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (env && *env && !g_tune_env_read) {
+            bh_status st = tune_load_locked(env, true);
+            if (st != BH_OK) return st;
+            g_tune_env_read = true;
+        }
+        cached = (flags & BH_TUNE_CACHED) && g_tune.find(key, hit) && valid_walk_shape(hit.shape);
+    }
     HIPCHK(launch_build(F.dev, fo->pos, fo->mass, s));
     HIPCHK(launch_upward(F.dev, s));
-    EventPair ev;
-    HIPCHK(hipEventCreate(&ev.a));
-    HIPCHK(hipEventCreate(&ev.b));
-    constexpr int kReps = 2;
+    int best_shape = F.walk_shape;
     float best = 0.0f;
-    int bw = F.walk_waves;
-    for (int k = 0; k < 4; ++k) {
-        const int w = kWalkWaves[k];
-        HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));   // warm-up
-        HIPCHK(hipEventRecord(ev.a, s));
-        for (int r = 0; r < kReps; ++r)
-            HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));
-        HIPCHK(hipEventRecord(ev.b, s));
-        HIPCHK(hipEventSynchronize(ev.b));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
-        ms /= kReps;
-        if (ms_out) ms_out[k] = ms;
-        if (k == 0 || ms < best) {
-            best = ms;
-            bw = w;
+    if (cached) {
+        best_shape = hit.shape;
+        HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, best_shape));
+        if (ms_out)
+            for (int k = 0; k < BH_TUNE_SHAPES; ++k) ms_out[k] = -1.0;
+    } else {
+        EventPair ev;
+        HIPCHK(hipEventCreate(&ev.a));
+        HIPCHK(hipEventCreate(&ev.b));
+        constexpr int kReps = 2;
+        for (int k = 0; k < BH_TUNE_SHAPES; ++k) {
+            const int w = tune_shape(k);
+            HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));   // warm-up
+            HIPCHK(hipEventRecord(ev.a, s));
+            for (int r = 0; r < kReps; ++r)
+                HIPCHK(launch_walk(F.dev, false, false, fo->acc, nullptr, nullptr, nullptr, nullptr, s, w));
+            HIPCHK(hipEventRecord(ev.b, s));
+            HIPCHK(hipEventSynchronize(ev.b));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+            ms /= kReps;
+            if (ms_out) ms_out[k] = ms;
+            if (k == 0 || ms < best) {
+                best = ms;
+                best_shape = w;
+            }
         }
     }
     bh_status st = bh_forest_check_err(F);
     if (st != BH_OK) return st;
-    if (bw != F.walk_waves) {
-        F.walk_waves = bw;
-        if (fo->graph) {   // recorded with the previous launch shape
-            HIPCHK(hipGraphExecDestroy(fo->graph));
-            fo->graph = nullptr;
+    forest_take_shape(fo, best_shape);
+    fo->have_acc = true;
+    if (!cached) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.put(key, bh_host::TuneEntry{best_shape, (double)best});
+        if (env && *env) {
+            st = tune_save_locked(env);
+            if (st != BH_OK) return st;
         }
     }
-    fo->have_acc = true;
-    if (waves_out) *waves_out = bw;
+    if (shape_out) *shape_out = best_shape;
     return BH_OK;
 }
 

@@ -10,6 +10,9 @@ constexpr int kMaxLevel = 21;          // 63-bit Morton keys: 21 octant digits
 constexpr int kTile = 4096;            // particles per sort / bbox tile
 constexpr int kGroup = 64;             // walk targets per wavefront
 constexpr int kWalkWaves[4] = {1, 2, 4, 8};   // walk launch shapes: wavefronts per block
+constexpr int kWalkWavesMask = 0xff;          // launch shape: wavefronts per block in the low byte,
+constexpr int kWalkPersistent = 0x100;        //   this bit for the persistent form (work queue)
+constexpr int kWalkQueues = 16;               // persistent walks: one group counter per walk variant
 constexpr int kStackMax = 160;         // >= 1 + 7 * 21 entries of (child block, lane mask)
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
@@ -124,6 +127,7 @@ struct ForestDev {
     double *red;                // reduction scratch (energy)
     double *pot;                // potential scratch (ntot)
     double *gbox;               // group criterion, per sorted row: its group's bounding box lo[3], hi[3]
+    uint32_t *wq;               // persistent walks: next group index, per walk variant (kWalkQueues)
 };
 
 // ---------------------------------------------------------------- helpers ---
@@ -274,9 +278,14 @@ hipError_t launch_upward(const ForestDev &f, hipStream_t s);     // masses, cent
 // totals only for the bodies of sorted ranks [wlo, whi).  Counting walks, each
 // nullable: work, each body's share of its group's wavefront work; gwork, that
 // work per walk group (indexed by the group's first rank / 64 in its simulation).
+// shape: wavefronts per workgroup, with kWalkPersistent for the persistent form
+// (counting walks always take the grid form with 4).
 hipError_t launch_walk(const ForestDev &f, bool stats, bool want_pot, double *acc, double *pot, int64_t *n_mono,
-                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int waves = 4, uint32_t wlo = 0,
+                       int64_t *n_p2p, uint64_t *hash, hipStream_t s, int shape = 4, uint32_t wlo = 0,
                        uint32_t whi = 0xffffffffu, int64_t *work = nullptr, int64_t *gwork = nullptr);
+// Workgroups of a persistent launch of `kernel` with `block` threads: as many as the
+// current device holds at once, at most nb.
+uint32_t persistent_blocks(const void *kernel, uint32_t nb, int block);
 // Cost zones over n bodies: per body (gathered through the sort order from two
 // caller-order arrays) when group_cost is null, else per 64-body walk group (group
 // g costs its body count plus group_cost[g]; bounds on group boundaries).

@@ -30,7 +30,7 @@ struct ForestHost {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bh_ctx *ctx = nullptr;
-    int walk_waves = 4;   // walk launch shape: wavefronts per workgroup (bh_forest_autotune)
+    int walk_shape = 4;   // walk launch shape: wavefronts per workgroup, kWalkPersistent (bh_forest_autotune)
 };
 
 struct bh_tree {

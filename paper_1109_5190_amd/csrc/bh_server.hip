@@ -128,7 +128,7 @@ bool bh_server::iterate(std::vector<uint64_t> &ids) {
     if (launch_drift(D, nullptr, nullptr, kPhaseDrift, s) != hipSuccess) return false;
     if (launch_build(D, nullptr, nullptr, s) != hipSuccess) return false;
     if (launch_upward(D, s) != hipSuccess) return false;
-    if (launch_walk(D, false, any_finish, nullptr, nullptr, nullptr, nullptr, nullptr, s, F.walk_waves) != hipSuccess) return false;
+    if (launch_walk(D, false, any_finish, nullptr, nullptr, nullptr, nullptr, nullptr, s, F.walk_shape) != hipSuccess) return false;
     if (launch_kick(D, nullptr, nullptr, kPhaseKick2, s) != hipSuccess) return false;
     if (launch_kick(D, nullptr, nullptr, kPhaseKick1, s) != hipSuccess) return false;
     std::vector<double> kw(2 * (size_t)nseg, 0.0);

@@ -26,14 +26,11 @@ namespace bh {
 // bounding box instead of its own position, in FP64 as the oracle writes it
 // (group_accepts), so the FP32 band is not used; pair and monopole terms are the
 // per-body walk's.
-template <bool STATS, bool POT, int W, bool QUAD, bool SOFT, bool GROUP>
-__global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
-    __shared__ WaveLds32 lds_all[W];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    WaveLds32 &L = lds_all[wave];
-    const uint32_t gi = blockIdx.x * W + wave;
-    if (gi >= f.ngroups) return;
-    if (uni(f.err[kErrWordTree]) & kErrTree) return;   // tree inconsistent: never walk it
+//
+// One walk group (gi < f.ngroups) on one wavefront with its LDS block L.
+template <bool STATS, bool POT, bool QUAD, bool SOFT, bool GROUP>
+__device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &out, WaveLds32 &L, const int lane,
+                                             const uint32_t gi) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
@@ -419,38 +416,75 @@ __global__ void __launch_bounds__(64 * W) k_walk32(ForestDev f, WalkOut out) {
 }
 
 
-template <bool STATS, bool POT, int W>
-static void launch_w32(const ForestDev &f, const WalkOut &o, hipStream_t s) {
-    const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
-    if (f.has32 & var_bit(false, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true, false>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(true, false)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, true, false>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(false, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false, false>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(true, true)) hipLaunchKernelGGL((k_walk32<STATS, POT, W, true, false, false>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(false, false, true))
-        hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, true, true>), g, b, 0, s, f, o);
-    if (f.has32 & var_bit(false, true, true))
-        hipLaunchKernelGGL((k_walk32<STATS, POT, W, false, false, true>), g, b, 0, s, f, o);
-}
-
-template <bool POT>
-static void launch_w32_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
-    switch (W) {
-        case 1: launch_w32<false, POT, 1>(f, o, s); break;
-        case 2: launch_w32<false, POT, 2>(f, o, s); break;
-        case 8: launch_w32<false, POT, 8>(f, o, s); break;
-        default: launch_w32<false, POT, 4>(f, o, s); break;
+// Walk launches.  Grid form: W wavefronts per workgroup, wavefront w of workgroup b
+// walks group b W + w.  Persistent form (PERSIST): as many workgroups as the device
+// holds at once; each wavefront takes the next group index from the counter q (one
+// atomic add per group, zero at launch) until the index passes the last group, so
+// a wavefront that finishes early starts another group at once and a workgroup's
+// LDS is held only while groups remain.  The form changes no result.
+template <bool STATS, bool POT, int W, bool QUAD, bool SOFT, bool GROUP, bool PERSIST>
+__global__ void __launch_bounds__(64 * W, (PERSIST && SOFT && !QUAD && !POT) ? 8 : 1) k_walk32(ForestDev f, WalkOut out, uint32_t *q) {
+    __shared__ WaveLds32 lds_all[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;   // tree inconsistent: never walk it
+    if (!PERSIST) {
+        const uint32_t gi = blockIdx.x * W + wave;
+        if (gi < f.ngroups) walk32_group<STATS, POT, QUAD, SOFT, GROUP>(f, out, lds_all[wave], lane, gi);
+        return;
+    }
+    for (;;) {
+        uint32_t gi = 0;
+        if (lane == 0) gi = atomicAdd(q, 1u);
+        gi = uni((uint32_t)__shfl((int)gi, 0, 64));
+        if (gi >= f.ngroups) break;
+        wave_sync();
+        walk32_group<STATS, POT, QUAD, SOFT, GROUP>(f, out, lds_all[wave], lane, gi);
     }
 }
 
-void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
+// Variant v of the FP32 family: (QUAD, SOFT, GROUP), its counter slot is v.
+template <bool STATS, bool POT, int W, bool PERSIST>
+static void launch_w32(const ForestDev &f, const WalkOut &o, hipStream_t s) {
+    const uint32_t nb = (f.ngroups + W - 1) / W;
+#define BH_W32(v, QUAD, SOFT, GROUP)                                                                       \
+    if (f.has32 & var_bit(QUAD, !(SOFT), GROUP)) {                                                        \
+        auto k = k_walk32<STATS, POT, W, QUAD, SOFT, GROUP, PERSIST>;                                     \
+        const dim3 g(PERSIST ? persistent_blocks((const void *)k, nb, 64 * W) : nb), b(64 * W);           \
+        hipLaunchKernelGGL(k, g, b, 0, s, f, o, f.wq + (v));                                             \
+    }
+    BH_W32(0, false, true, false);
+    BH_W32(1, true, true, false);
+    BH_W32(2, false, false, false);
+    BH_W32(3, true, false, false);
+    BH_W32(4, false, true, true);
+    BH_W32(5, false, false, true);
+#undef BH_W32
+}
+
+template <bool POT, bool PERSIST>
+static void launch_w32_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
+    switch (W) {
+        case 1: launch_w32<false, POT, 1, PERSIST>(f, o, s); break;
+        case 2: launch_w32<false, POT, 2, PERSIST>(f, o, s); break;
+        case 8: launch_w32<false, POT, 8, PERSIST>(f, o, s); break;
+        default: launch_w32<false, POT, 4, PERSIST>(f, o, s); break;
+    }
+}
+
+void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int shape, hipStream_t s) {
     if (!f.has32) return;
+    const int W = shape & kWalkWavesMask;
+    const bool persist = (shape & kWalkPersistent) != 0;
     if (stats) {   // the counting walks use one launch shape
-        if (pot) launch_w32<true, true, 4>(f, o, s);
-        else launch_w32<true, false, 4>(f, o, s);
+        if (pot) launch_w32<true, true, 4, false>(f, o, s);
+        else launch_w32<true, false, 4, false>(f, o, s);
+    } else if (persist) {
+        if (pot) launch_w32_shape<true, true>(f, o, W, s);
+        else launch_w32_shape<false, true>(f, o, W, s);
     } else if (pot) {
-        launch_w32_shape<true>(f, o, W, s);
+        launch_w32_shape<true, false>(f, o, W, s);
     } else {
-        launch_w32_shape<false>(f, o, W, s);
+        launch_w32_shape<false, false>(f, o, W, s);
     }
 }
 

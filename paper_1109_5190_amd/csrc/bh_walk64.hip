@@ -8,14 +8,11 @@ namespace bh {
 
 // GROUP (the group-criterion variant): each lane tests cubes against its group's
 // bounding box (group_accepts) instead of its own position.
-template <bool STATS, bool POT, int W, bool QUAD, bool GROUP>
-__global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
-    __shared__ WaveLds64<QUAD> lds_all[W];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    WaveLds64<QUAD> &L = lds_all[wave];
-    const uint32_t gi = blockIdx.x * W + wave;
-    if (gi >= f.ngroups) return;
-    if (uni(f.err[kErrWordTree]) & kErrTree) return;   // tree inconsistent: never walk it
+//
+// One walk group (gi < f.ngroups) on one wavefront with its LDS block L.
+template <bool STATS, bool POT, bool QUAD, bool GROUP>
+__device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &out, WaveLds64<QUAD> &L,
+                                             const int lane, const uint32_t gi) {
     const GroupDesc gd = f.groups[gi];
     const uint32_t sid = uni(gd.seg);
     const SegDesc &sd = f.seg[sid];
@@ -240,34 +237,67 @@ __global__ void __launch_bounds__(64 * W) k_walk64(ForestDev f, WalkOut out) {
 }
 
 
-template <bool STATS, bool POT, int W>
-static void launch_w64(const ForestDev &f, const WalkOut &o, hipStream_t s) {
-    const dim3 g((f.ngroups + W - 1) / W), b(64 * W);
-    if (f.has64 & (var_bit(false, false) | var_bit(false, true)))
-        hipLaunchKernelGGL((k_walk64<STATS, POT, W, false, false>), g, b, 0, s, f, o);
-    if (f.has64 & kVarQuadBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, true, false>), g, b, 0, s, f, o);
-    if (f.has64 & kVarGroupBits) hipLaunchKernelGGL((k_walk64<STATS, POT, W, false, true>), g, b, 0, s, f, o);
-}
-
-template <bool POT>
-static void launch_w64_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
-    switch (W) {
-        case 1: launch_w64<false, POT, 1>(f, o, s); break;
-        case 2: launch_w64<false, POT, 2>(f, o, s); break;
-        case 8: launch_w64<false, POT, 8>(f, o, s); break;
-        default: launch_w64<false, POT, 4>(f, o, s); break;
+// Grid and persistent launch forms, as for the FP32 walk.
+template <bool STATS, bool POT, int W, bool QUAD, bool GROUP, bool PERSIST>
+__global__ void __launch_bounds__(64 * W, (PERSIST && !QUAD && !POT && !GROUP) ? 7 : 1) k_walk64(ForestDev f, WalkOut out, uint32_t *q) {
+    __shared__ WaveLds64<QUAD> lds_all[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (uni(f.err[kErrWordTree]) & kErrTree) return;   // tree inconsistent: never walk it
+    if (!PERSIST) {
+        const uint32_t gi = blockIdx.x * W + wave;
+        if (gi < f.ngroups) walk64_group<STATS, POT, QUAD, GROUP>(f, out, lds_all[wave], lane, gi);
+        return;
+    }
+    for (;;) {
+        uint32_t gi = 0;
+        if (lane == 0) gi = atomicAdd(q, 1u);
+        gi = uni((uint32_t)__shfl((int)gi, 0, 64));
+        if (gi >= f.ngroups) break;
+        wave_sync();
+        walk64_group<STATS, POT, QUAD, GROUP>(f, out, lds_all[wave], lane, gi);
     }
 }
 
-void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s) {
+// Variant v of the FP64 family: (QUAD, GROUP), its counter slot is 8 + v.
+template <bool STATS, bool POT, int W, bool PERSIST>
+static void launch_w64(const ForestDev &f, const WalkOut &o, hipStream_t s) {
+    const uint32_t nb = (f.ngroups + W - 1) / W;
+#define BH_W64(v, present, QUAD, GROUP)                                                                    \
+    if (present) {                                                                                        \
+        auto k = k_walk64<STATS, POT, W, QUAD, GROUP, PERSIST>;                                          \
+        const dim3 g(PERSIST ? persistent_blocks((const void *)k, nb, 64 * W) : nb), b(64 * W);           \
+        hipLaunchKernelGGL(k, g, b, 0, s, f, o, f.wq + 8 + (v));                                         \
+    }
+    BH_W64(0, f.has64 & (var_bit(false, false) | var_bit(false, true)), false, false);
+    BH_W64(1, f.has64 & kVarQuadBits, true, false);
+    BH_W64(2, f.has64 & kVarGroupBits, false, true);
+#undef BH_W64
+}
+
+template <bool POT, bool PERSIST>
+static void launch_w64_shape(const ForestDev &f, const WalkOut &o, int W, hipStream_t s) {
+    switch (W) {
+        case 1: launch_w64<false, POT, 1, PERSIST>(f, o, s); break;
+        case 2: launch_w64<false, POT, 2, PERSIST>(f, o, s); break;
+        case 8: launch_w64<false, POT, 8, PERSIST>(f, o, s); break;
+        default: launch_w64<false, POT, 4, PERSIST>(f, o, s); break;
+    }
+}
+
+void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int shape, hipStream_t s) {
     if (!f.has64) return;
+    const int W = shape & kWalkWavesMask;
+    const bool persist = (shape & kWalkPersistent) != 0;
     if (stats) {   // the counting walks use one launch shape
-        if (pot) launch_w64<true, true, 4>(f, o, s);
-        else launch_w64<true, false, 4>(f, o, s);
+        if (pot) launch_w64<true, true, 4, false>(f, o, s);
+        else launch_w64<true, false, 4, false>(f, o, s);
+    } else if (persist) {
+        if (pot) launch_w64_shape<true, true>(f, o, W, s);
+        else launch_w64_shape<false, true>(f, o, W, s);
     } else if (pot) {
-        launch_w64_shape<true>(f, o, W, s);
+        launch_w64_shape<true, false>(f, o, W, s);
     } else {
-        launch_w64_shape<false>(f, o, W, s);
+        launch_w64_shape<false, false>(f, o, W, s);
     }
 }
 

@@ -148,10 +148,11 @@ __device__ __forceinline__ bool group_accepts(double cx, double cy, double cz, d
 }
 
 // Launchers of one kernel family each (defined in their own translation unit):
-// W wavefronts (one 64-body walk group each) per workgroup; stats: the counting
-// variant (totals, per-body counts and checksums); pot: also the potential.  Each
-// launches the variants (expansion order, softening, opening test) its forest holds.
-void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s);
-void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int W, hipStream_t s);
+// shape, the launch shape (wavefronts per workgroup, each walking one 64-body group
+// at a time, and the persistent bit); stats: the counting variant (totals, per-body
+// counts and checksums); pot: also the potential.  Each launches the variants
+// (expansion order, softening, opening test) its forest holds.
+void launch_walk32_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int shape, hipStream_t s);
+void launch_walk64_family(const ForestDev &f, const WalkOut &o, bool stats, bool pot, int shape, hipStream_t s);
 
 }  // namespace bh

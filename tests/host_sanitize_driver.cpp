@@ -1,8 +1,10 @@
 // Exercises the library's host-only logic (workspace layouts, interaction-list
 // buffer layouts, the server's first-fit arena and its first-come first-served
-// admission) for a build under AddressSanitizer and UndefinedBehaviorSanitizer,
+// admission, the tuning cache and its JSON reader) for a build under
+// AddressSanitizer and UndefinedBehaviorSanitizer,
 // and checks its invariants against plain reference models.  Test
 // infrastructure: exit status 0 and "all cases ok" when every check holds.
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -194,12 +196,97 @@ static void admission(std::mt19937_64 &rng) {
     CHECK(got.size() == 1 && got[0].second == 4096 && q.empty());
 }
 
+static TuneKey random_key(std::mt19937_64 &rng) {
+    static const char *devs[] = {"gfx950:256", "gfx942:304", "a\"b\\c", "tab\there"};
+    static const char *precs[] = {"fp32", "fp64", "mixed"};
+    TuneKey k;
+    k.device = devs[rng() % 4];
+    k.n_log2 = (int)(rng() % 63);
+    k.sims_log2 = (int)(rng() % 32);
+    k.theta_c = (int)(rng() % 1000001);
+    k.precision = precs[rng() % 3];
+    return k;
+}
+
+static void tune_cache(std::mt19937_64 &rng) {
+    static const int shapes[] = {1, 2, 4, 8, 0x101, 0x102, 0x104, 0x108};
+    // round trips: what is written reads back as the same entries
+    for (int t = 0; t < 300; ++t) {
+        TuneCache c;
+        std::map<TuneKey, TuneEntry> model;
+        const int n = (int)(rng() % 20);
+        for (int i = 0; i < n; ++i) {
+            const TuneKey k = random_key(rng);
+            const TuneEntry e{shapes[rng() % 8], (double)(rng() % 100000) / 8.0};
+            c.put(k, e);
+            model[k] = e;
+        }
+        CHECK(c.size() == model.size());
+        TuneCache d;
+        std::string err;
+        CHECK(d.merge_json(c.to_json(), err));
+        CHECK(d.size() == model.size());
+        for (const auto &kv : model) {
+            TuneEntry e;
+            CHECK(d.find(kv.first, e) && e.shape == kv.second.shape && std::fabs(e.ms - kv.second.ms) <= 1e-5 * (1 + kv.second.ms));
+        }
+        // mutated texts: parse or refuse, never read out of bounds; a refusal leaves the cache as it was
+        const std::string text = c.to_json();
+        for (int m = 0; m < 40; ++m) {
+            std::string x = text;
+            const int kind = (int)(rng() % 4);
+            if (x.empty()) break;
+            const size_t at = rng() % x.size();
+            if (kind == 0) x[at] = (char)(rng() % 256);
+            else if (kind == 1) x.erase(at, 1 + rng() % 8);
+            else if (kind == 2) x.insert(at, 1, "{}[]\",:\\0e-9tn"[rng() % 14]);
+            else x.resize(at);
+            TuneCache e = d;
+            const size_t before = e.size();
+            std::string er;
+            if (!e.merge_json(x, er)) {
+                CHECK(e.size() == before && !er.empty());
+            }
+        }
+    }
+    // schema errors are refused with the cache unchanged
+    const char *bad[] = {
+        "", "[]", "{}", "null", "{\"format\": \"bh-tune-cache\", \"version\": 2, \"entries\": []}",
+        "{\"format\": \"other\", \"version\": 1, \"entries\": []}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": {}}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [], \"x\": 1}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3, "
+        "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp32\", \"shape\": 3, \"ms\": 1}]}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3.5, "
+        "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp32\", \"shape\": 4, \"ms\": 1}]}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3, "
+        "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp16\", \"shape\": 4, \"ms\": 1}]}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3, "
+        "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp32\", \"shape\": 4, \"ms\": -1}]}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"version\": 1, \"entries\": []}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [1e999]}",
+        "[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]",
+    };
+    TuneCache c;
+    c.put(TuneKey{"gfx950:256", 20, 0, 50, "fp32"}, TuneEntry{4, 2.5});
+    for (const char *b : bad) {
+        std::string err;
+        CHECK(!c.merge_json(b, err));
+        CHECK(c.size() == 1 && !err.empty());
+    }
+    std::string err;
+    CHECK(c.merge_json("{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": []}", err) && c.size() == 1);
+    CHECK(valid_shape(0x104) && !valid_shape(0x200) && !valid_shape(3) && !valid_shape(-4) && !valid_shape(0));
+    CHECK(floor_log2(0) == 0 && floor_log2(1) == 0 && floor_log2(1048576) == 20 && floor_log2(1048575) == 19);
+}
+
 int main() {
     std::mt19937_64 rng(20260201);
     layouts(rng);
     list_layouts(rng);
     arena(rng);
     admission(rng);
+    tune_cache(rng);
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);
         return 1;

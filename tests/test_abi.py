@@ -122,7 +122,9 @@ REQUIRED = ["bh_ctx_create", "bh_ctx_destroy", "bh_ctx_sync", "bh_last_error", "
             "bh_upward", "bh_forces", "bh_forces_stats", "bh_tree_export", "bh_tree_free", "bh_sim_create",
             "bh_step", "bh_energy", "bh_sim_destroy", "bh_forest_create", "bh_forest_step", "bh_forest_destroy",
             "bh_server_create", "bh_server_submit", "bh_server_poll", "bh_server_fetch", "bh_server_cancel",
-            "bh_server_destroy", "bh_ic_generate", "bh_ic_workspace_bytes"]
+            "bh_server_destroy", "bh_ic_generate", "bh_ic_workspace_bytes", "bh_forest_autotune",
+            "bh_tree_set_walk_shape", "bh_sim_set_walk_shape", "bh_forest_set_walk_shape", "bh_tune_cache_load",
+            "bh_tune_cache_save", "bh_tune_cache_clear", "bh_tune_cache_size"]
 
 
 def _decl(name):
@@ -144,7 +146,9 @@ def test_header_declares_the_boundary():
         assert f in stats
     codes = dict(re.findall(r"(BH_E_[A-Z]+|BH_OK) = (\d+)", text))
     assert codes == {"BH_OK": "0", "BH_E_INVAL": "1", "BH_E_NOMEM": "2", "BH_E_DEVICE": "3", "BH_E_BUSY": "4",
-                     "BH_E_NOTFOUND": "5", "BH_E_OVERFLOW": "6", "BH_E_CANCELLED": "7"}
+                     "BH_E_NOTFOUND": "5", "BH_E_OVERFLOW": "6", "BH_E_CANCELLED": "7", "BH_E_IO": "8"}
+    assert "uint32_t flags, int32_t *shape_out, double *ms_out" in _decl("bh_forest_autotune")
+    assert re.search(r"#define BH_WALK_PERSISTENT 0x100\b", text) and re.search(r"#define BH_TUNE_SHAPES 8\b", text)
     # every device buffer comes from the caller: workspace arguments on the calls that need scratch
     for name in ("bh_build", "bh_sim_create", "bh_forest_create", "bh_ic_generate"):
         assert "void *ws" in _decl(name), name
