@@ -90,9 +90,10 @@ def parse():
     ap.add_argument("--serve-precisions", default="fp32,fp64",
                     help="serving runs at --serve-rate; the first is repeated near its measured capacity")
     ap.add_argument("--no-leaf16", action="store_true", help="skip the leaf_cap 16 leg")
-    ap.add_argument("--workload", choices=("plummer1m", "sweep", "batch"), default="plummer1m",
+    ap.add_argument("--workload", choices=("plummer1m", "sweep", "batch", "serving"), default="plummer1m",
                     help="plummer1m: the headline line; sweep: the two-sphere and cube systems of 2^22 over "
-                         "theta; batch: 512 simulations as one forest (each prints its own JSON line)")
+                         "theta; batch: 512 simulations as one forest; serving: the request stream with "
+                         "2000 requests in FP32 and FP64 and an arrival-rate sweep (each prints its own JSON line)")
     ap.add_argument("--sample", type=int, default=2048, help="oracle targets per error check (sweep, batch)")
     return ap.parse_args()
 
@@ -310,12 +311,16 @@ def serve(a, bh, ctx, torch, precision, rate, nreq):
             time.sleep(min(0.001, max(0.0, r["t"] - (sv.now() - t0))))
         ids.append(sv.submit(r["n"], r["steps"], r["kind"], r["seed"], p, 1e-3, release=True))
     done = []
-    for rid in ids:
+    t_note = time.time()
+    for k, rid in enumerate(ids):
         while True:
             st = sv.poll(rid)
             if st["state"] in ("done", "failed", "cancelled"):
                 break
             time.sleep(0.002)
+            if time.time() - t_note > 20.0:   # progress of a long run
+                print(f"# serving {precision}: {k} of {len(ids)} requests finished", file=sys.stderr, flush=True)
+                t_note = time.time()
         done.append(st)
     sv.close()
     ok = [d for d in done if d["state"] == "done"]
@@ -337,6 +342,37 @@ def serve(a, bh, ctx, torch, precision, rate, nreq):
           f"p99 {out['p99_latency_s']:.3f}s, {out['throughput_particle_steps_per_s']:.3e} particle-steps/s",
           file=sys.stderr, flush=True)
     return out
+
+
+def serving_c5(a, bh, torch):
+    """Serving as specified for the request stream: R = 2000 requests at 200 req/s (exponential
+    gaps, seed 7), one FP32 run and one FP64 run; then arrival rates below and around the FP32
+    capacity (R = 400 each) for the highest rate whose latency stays bounded: the server keeps up
+    (completed work per second >= 95 % of the offered load) and the mean queue wait stays below a
+    quarter of the mean service time."""
+    import numpy as np
+
+    import icgen
+    ctx = ctx_of(bh, torch)
+    runs = {prec: serve(a, bh, ctx, torch, prec, 200.0, 2000) for prec in ("fp32", "fp64")}
+    # rates in units of the capacity for the sweep's own (smaller) request set
+    mean_work = float(np.mean([r["n"] * r["steps"] for r in icgen.request_stream(400, 200.0, master_seed=7)]))
+    lam_cap = runs["fp32"]["throughput_particle_steps_per_s"] / mean_work
+    sweep = []
+    for frac in (0.75, 0.9, 1.0, 1.1, 1.25):
+        r = serve(a, bh, ctx, torch, "fp32", frac * lam_cap, 400)
+        r["bounded"] = bool(r["throughput_particle_steps_per_s"] >= 0.95 * r["offered_particle_steps_per_s"] and
+                            r["mean_queue_wait_s"] <= 0.25 * r["mean_service_s"])
+        sweep.append(r)
+    ok = [r["rate_req_per_s"] for r in sweep if r["bounded"]]
+    return {"metric": "served p99 latency, 2000 requests at 200 req/s (FP32)",
+            "value": runs["fp32"]["p99_latency_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "request stream: Poisson arrivals at 200 req/s, R=2000, N log-uniform in "
+                                   "[4096, 4194304], steps uniform 1..100, Plummer or cube 50/50, theta 0.5, "
+                                   "eps 0.01, dt 1e-3, seed 7"},
+            "runs": runs, "capacity_req_per_s": lam_cap, "rate_sweep": sweep,
+            "highest_bounded_rate_req_per_s": max(ok) if ok else None}
 
 
 def leaf16(a, bh, torch, stream, pos0, vel0, mass, s):
@@ -411,6 +447,9 @@ def main():
         return
     if a.workload == "batch":
         print(json.dumps(batch(a, bh, torch)))
+        return
+    if a.workload == "serving":
+        print(json.dumps(serving_c5(a, bh, torch)))
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
