@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--serve-precisions", default="fp32,fp64",
                     help="serving runs at --serve-rate; the first is repeated near its measured capacity")
     ap.add_argument("--no-leaf16", action="store_true", help="skip the leaf_cap 16 leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the two-sphere theta leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-simulation batch leg")
     ap.add_argument("--workload", choices=("plummer1m", "sweep", "batch", "serving"), default="plummer1m",
                     help="plummer1m: the headline line; sweep: the two-sphere and cube systems of 2^22 over "
                          "theta; batch: 512 simulations as one forest; serving: the request stream with "
@@ -375,6 +377,64 @@ def serving_c5(a, bh, torch):
             "highest_bounded_rate_req_per_s": max(ok) if ok else None}
 
 
+def theta_two_spheres(a, bh, torch, stream):
+    """The theta sweep's two-sphere system (2 x 2^21 at +-(5,0,0), eps 0.005, per-body monopole) in
+    both precisions: force evaluations per second (build + upward + walk) and walk TFLOP/s at theta
+    0.3 / 0.5 / 0.7 / 1.0, with the error against the oracle on 256 sampled targets per theta (the
+    full sweep over both systems and every variant is `--workload sweep`)."""
+    import numpy as np
+
+    import icgen
+    import oracle
+    dev = torch.device("cuda:0")
+    ctx = ctx_of(bh, torch)
+    s = icgen.two_plummer(1 << 21, 3, 4)
+    pos, mass = torch.tensor(s.pos, device=dev), torch.tensor(s.mass, device=dev)
+    T = oracle.Tree(s.pos, s.mass, a.leaf_cap)
+    rng = np.random.default_rng(21)
+    tg = np.sort(rng.choice(s.n, 256, replace=False)).astype(np.int64)
+    tgd = torch.tensor(tg, device=dev)
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+    for theta in (0.3, 0.5, 0.7, 1.0):
+        ref = T.walk(theta, 0.005, 1.0, tg, nthreads=cores)
+        for prec in ("fp32", "fp64"):
+            p = bh.params(theta, 0.005, 1.0, a.leaf_cap, prec)
+            t = bh.Tree(ctx, pos, mass, p).upward()
+            tot = t.forces_stats()["totals"]
+            inter = tot["n_mono"] + tot["n_p2p"]
+            acc = t.forces()
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            w0, w1 = _events(torch)
+            reps = 3
+            e0.record(stream)
+            for _ in range(reps):
+                t.rebuild(pos, mass).upward()
+                t.forces(acc)
+            e1.record(stream)
+            w0.record(stream)
+            for _ in range(reps):
+                t.forces(acc)
+            w1.record(stream)
+            torch.cuda.synchronize()
+            ms_eval, ms_walk = e0.elapsed_time(e1) / reps, w0.elapsed_time(w1) / reps
+            rms, mx = _errors(acc[tgd].cpu().numpy(), ref["acc"])
+            peak = 157.3e12 if prec == "fp32" else 78.6e12
+            rows.append({"theta": theta, "precision": prec, "ms_force_eval": ms_eval,
+                         "mparticles_per_s": s.n / (ms_eval * 1e-3) / 1e6, "ms_walk": ms_walk,
+                         "interactions_per_particle": inter / s.n,
+                         "walk_tflops": FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / 1e12,
+                         "walk_frac_of_peak": FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / peak,
+                         "rms_rel_vs_oracle": rms, "max_rel_vs_oracle": mx})
+            print(f"# two spheres theta={theta} {prec}: eval {ms_eval:.3f} ms walk {ms_walk:.3f} ms rms {rms:.2e}",
+                  file=sys.stderr, flush=True)
+            del t
+    return {"system": "two unit-mass Plummer spheres of 2^21 at +-(5,0,0), seeds 3/4, eps 0.005, monopole, "
+                      f"leaf_cap {a.leaf_cap}", "n": s.n, "results": rows,
+            "error_sample": "256 random targets per theta against the oracle at the same settings"}
+
+
 def leaf16(a, bh, torch, stream, pos0, vel0, mass, s):
     """The headline configuration with leaves of up to 16 particles (FP32): step and walk
     times, interactions per particle and the error against the oracle on sampled targets."""
@@ -593,6 +653,12 @@ def main():
 
     if not a.no_leaf16:
         out["leaf_cap_16"] = leaf16(a, bh, torch, stream, pos0, vel0, mass, s)
+    if not a.no_sweep:
+        out["theta_sweep_two_spheres"] = theta_two_spheres(a, bh, torch, stream)
+    if not a.no_batch:
+        b = batch(a, bh, torch)
+        out["batch"] = {k: b[k] for k in ("metric", "value", "unit", "steps", "ms_per_step", "config", "autotune",
+                                          "force_error_vs_oracle")}
 
     if a.serve_requests > 0:
         runs = {}
