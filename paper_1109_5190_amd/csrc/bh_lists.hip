@@ -98,7 +98,9 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
             L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            L.sb[lane] = open_band(w, qx, qy, qz, rw);
+            const float2 band = open_band(w, qx, qy, qz, rw);
+            L.sbh[lane] = band.x;
+            L.sbl[lane] = band.y;
             L.sl[lane] = make_uint2(w.link, w.cnt);
             L.sc[lane] = make_uint2(w.gid, w.level);
         }
@@ -110,10 +112,10 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
             const float4 qa = L.sa[c];
             const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
             const float E2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-            uint64_t accm = ballot(E2 > L.sb[c].x) & emask;
+            uint64_t accm = ballot(E2 > L.sbh[c]) & emask;
             uint64_t open = emask & ~accm;
             if (open) {
-                const uint64_t ambm = ballot(!(E2 < L.sb[c].y)) & open;
+                const uint64_t ambm = ballot(!(E2 < L.sbl[c])) & open;
                 if (ambm) {
                     bool ex = false;
                     if (in_mask(ambm)) {

@@ -194,7 +194,7 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
     bool pend = true;
     uint32_t p_link = sid, p_cnt = 1u;
     uint64_t p_mask = ballot(live);
-    const size_t lane_off = (size_t)lane;
+    const uint32_t lane_off = (uint32_t)lane * (uint32_t)sizeof(WRec32);   // byte offset of lane c's record
     for (;;) {
         uint32_t link, nch;
         uint64_t emask;
@@ -214,8 +214,24 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
         if (STATS) wwork += nch;
         wave_sync();
         if ((uint32_t)lane < nch) {
-            const WRec32 *wb = f.w32 + link;   // wave-uniform base, lane offset
-            const WRec32 &w = wb[lane_off];
+            const ChildRecs32 cr(f.w32 + link);
+            const v4u32 r0 = cr.q(lane_off, 0), r1 = cr.q(lane_off, 1), r2q = cr.q(lane_off, 2);
+            WRec32 w;
+            w.cx = as_f64(r0.x, r0.y);
+            w.cy = as_f64(r0.z, r0.w);
+            w.cz = as_f64(r1.x, r1.y);
+            w.m = __uint_as_float(r1.z);
+            w.Sh = __uint_as_float(r1.w);
+            w.band0 = __uint_as_float(r2q.x);
+            w.band1 = __uint_as_float(r2q.y);
+            w.link = r2q.z;
+            w.cnt = r2q.w;
+            if (STATS || GROUP) {
+                const v4u32 r3 = cr.q(lane_off, 3);
+                w.gid = r3.x;
+                w.level = r3.y;
+                w.r2 = as_f64(r3.z, r3.w);
+            }
             const float qx = (float)__dsub_rn(w.cx, gx);
             const float qy = (float)__dsub_rn(w.cy, gy);
             const float qz = (float)__dsub_rn(w.cz, gz);
@@ -226,7 +242,9 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
                 L.x.g.cz[lane] = w.cz;
                 L.x.g.r2[lane] = w.r2;
             } else {
-                L.sb[lane] = open_band(w, qx, qy, qz, rw);
+                const float2 band = open_band(w, qx, qy, qz, rw);
+                L.sbh[lane] = band.x;
+                L.sbl[lane] = band.y;
             }
             L.sl[lane] = make_uint2(w.link, w.cnt);
             if (STATS) L.sc[lane] = make_uint2(w.gid, w.level);
@@ -250,11 +268,11 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
                 accm = ballot(group_accepts(L.x.g.cx[c], L.x.g.cy[c], L.x.g.cz[c], L.x.g.r2[c], blo, bhi, theta2)) &
                        emask;
             } else {
-                accm = ballot(E2 > L.sb[c].x) & emask;
+                accm = ballot(E2 > L.sbh[c]) & emask;
             }
             open = emask & ~accm;
             if (open) {
-                const uint64_t ambm = GROUP ? 0 : ballot(!(E2 < L.sb[c].y)) & open;
+                const uint64_t ambm = GROUP ? 0 : ballot(!(E2 < L.sbl[c])) & open;
                 if (ambm) {
                     // within the FP32 rounding bound of the threshold: decide exactly in FP64
                     bool ex = false;

@@ -86,7 +86,7 @@ struct WalkOut {
 struct WaveLds32 {
     uint4 stk[kStackMax];
     float4 sa[8];          // child: centre rel g (x, y, z), mass
-    float2 sb[8];          // child: accept above hi, decide in FP64 at or above lo (this wavefront)
+    float sbh[8], sbl[8];  // child: accept above sbh, decide in FP64 at or above sbl (this wavefront)
     uint2 sl[8];           // child: link, cnt
     uint2 sc[8];           // child: gid, level
     union {
@@ -103,6 +103,24 @@ struct WaveLds32 {
                            //                        32 particles as (hi, mass), (lo, 0))
     uint4 ovf[8];          // opened leaves that did not fit the queue: first rank, count, mask
 };
+
+// The FP32 walk records of a stack entry's children (at most 8, consecutive), read by
+// lane c with buffer loads through one scalar resource whose base is the first
+// child's record, so the per-lane address is a 32-bit offset (no 64-bit vector
+// address arithmetic per entry); lanes past the 8 records read zeros.
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+constexpr int kBufferWord3 = 0x00020000;   // buffer resource word 3 for raw 32-bit access (gfx9 family)
+struct ChildRecs32 {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ explicit ChildRecs32(const WRec32 *first)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<WRec32 *>(first), (short)0, 8 * (int)sizeof(WRec32),
+                                               kBufferWord3)) {}
+    // record fields by 16-byte quarter: (cx, cy), (cz, m, Sh), (band0, band1, link, cnt), (gid, level, r2)
+    __device__ __forceinline__ v4u32 q(uint32_t lane_off, uint32_t quarter) const {
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane_off, (int)(16u * quarter), 0);
+    }
+};
+__device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) { return __hiloint2double((int)hi, (int)lo); }
 
 // Opening thresholds of a child for one wavefront (FP32 walks): E2 > hi accepts,
 // E2 < lo opens, anything between is decided in FP64.  q: the child's centre
