@@ -30,6 +30,12 @@ METRIC = "BH force-evals Mparticles/s at theta=0.5, N=1M (FP32 vs FP64); served 
 FP32_PEAK = 157.3e12     # MI355X vector FP32 (packed issue)
 FP64_PEAK = 78.6e12      # MI355X vector FP64
 FLOPS_PER_INTERACTION = 20
+FP32_NONPACKED_PEAK = 78.6e12   # the same VALU without packed FP32 issue (how the library is compiled)
+HBM_PEAK = 8.0e12               # MI355X HBM3E
+# algorithmic bytes per particle of one rebuild with its upward pass (8-bit digits): bbox 24,
+# keys 36, sort 8 x 24, permute ~128, node build ~8 + ~48 per node, upward ~32 + ~56 per node,
+# with ~1.45 nodes per particle: about 450
+BUILD_BYTES_PER_PARTICLE = 450
 TRAFFIC_SUMMARY = ROOT / "profiles" / "hbm_traffic_plummer_1M.md"
 VALU_SUMMARY = ROOT / "profiles" / "walk_instruction_mix_plummer_1M.md"
 WALK_SOURCES = [ROOT / "paper_1109_5190_amd" / "csrc" / f for f in ("bh_walk32.hip", "bh_walk_common.h", "bh_common.h")]
@@ -293,6 +299,26 @@ def one_gpu_share(a, tree, stream, torch, ms_walk, acc_full):
     print(f"# one GPU's share of {G}: slowest range {out['max_ms']:.3f} ms, imbalance {out['imbalance']:.3f}",
           file=sys.stderr, flush=True)
     return out
+
+
+def copy_bandwidth(torch):
+    """Device-to-device copy of 2 GiB (read + write bytes / time), the HBM rate a plain streaming
+    kernel reaches on this GPU."""
+    x = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 2 * x.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y
+    torch.cuda.empty_cache()
+    return bw
 
 
 def serve(a, bh, ctx, torch, precision, rate, nreq):
@@ -616,7 +642,8 @@ def main():
                    "n": a.n, "theta": a.theta, "eps": a.eps, "leaf_cap": a.leaf_cap, "dt": a.dt},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": walk_traffic(a.n) if head == "fp32" else None,
-                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated)",
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by their reading for "
+                                     "k_keys, whose bytes per dispatch are known)",
                      "kernel": f"k_walk32 ({FLOPS_PER_INTERACTION} flops x {r['interactions']} interactions "
                                f"per launch / {r['ms_walk']:.3f} ms)"},
         "walk_only": {"ms": r["ms_walk"], "mparticles_per_s": a.n / (r["ms_walk"] * 1e-3) / 1e6,
@@ -625,12 +652,18 @@ def main():
                       "wave_visits": r["wave_visits"], "wave_entries": r["wave_entries"],
                       "wave_accepts": r["wave_accepts"], "wave_leaves": r["wave_leaves"],
                       "lane_utilisation": r["interactions"] / max(1, 64 * r["wave_visits"]),
+                      "frac_of_nonpacked_fp32_peak": (achieved / FP32_NONPACKED_PEAK if head == "fp32" else None),
                       "valu_insts_per_launch": walk_valu(a.n) if head == "fp32" else None,
                       "valu_lane_slots_per_interaction": (64 * walk_valu(a.n) / r["interactions"]
                                                           if head == "fp32" and walk_valu(a.n) else None),
                       "valu_source": "SQ_INSTS_VALU of the committed counter summary, when taken on this walk "
                                      "source (else null)"},
         "build_upward_ms": r["ms_build_upward"],
+        "build_roofline": {"bound": "hbm", "bytes_per_particle_model": BUILD_BYTES_PER_PARTICLE,
+                           "achieved": BUILD_BYTES_PER_PARTICLE * a.n / (r["ms_build_upward"] * 1e-3) / 1e12,
+                           "peak": HBM_PEAK / 1e12, "unit": "TB/s",
+                           "frac": BUILD_BYTES_PER_PARTICLE * a.n / (r["ms_build_upward"] * 1e-3) / HBM_PEAK,
+                           "measured_copy_TBps": copy_bandwidth(torch)},
     }
     if r.get("lists"):
         out["two_phase_lists"] = r["lists"]
