@@ -267,10 +267,13 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
             if (GROUP) {
                 accm = ballot(group_accepts(L.x.g.cx[c], L.x.g.cy[c], L.x.g.cz[c], L.x.g.r2[c], blo, bhi, theta2)) &
                        emask;
+                open = emask & ~accm;
             } else {
-                accm = ballot(E2 > L.sbh[c]) & emask;
+                // the lanes of the entry that do not accept (an and-not that sets the scalar condition
+                // for the branch below), then the accepting ones
+                open = emask & ~ballot(E2 > L.sbh[c]);
+                accm = emask & ~open;
             }
-            open = emask & ~accm;
             if (open) {
                 const uint64_t ambm = GROUP ? 0 : ballot(!(E2 < L.sbl[c])) & open;
                 if (ambm) {
