@@ -490,7 +490,7 @@ public:
             if (!th || th->kind != JVal::Num || !(th->num >= 0.0) || th->num > 1.0e4) return bad(err, "bad theta");
             if (!pr || pr->kind != JVal::Str || (pr->str != "fp32" && pr->str != "fp64" && pr->str != "mixed"))
                 return bad(err, "bad precision");
-            if (!sh || sh->kind != JVal::Num || sh->num != std::floor(sh->num) || sh->num > 1e6 ||
+            if (!sh || sh->kind != JVal::Num || sh->num != std::floor(sh->num) || sh->num < 0.0 || sh->num > 1e6 ||
                 !valid_shape((long)sh->num))
                 return bad(err, "bad shape");
             if (!ms || ms->kind != JVal::Num || !(ms->num >= 0.0)) return bad(err, "bad ms");

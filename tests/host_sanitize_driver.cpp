@@ -263,6 +263,8 @@ static void tune_cache(std::mt19937_64 &rng) {
         "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp16\", \"shape\": 4, \"ms\": 1}]}",
         "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3, "
         "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp32\", \"shape\": 4, \"ms\": -1}]}",
+        "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [{\"device\": \"g\", \"n_log2\": 3, "
+        "\"sims_log2\": 0, \"theta\": 0.5, \"precision\": \"fp32\", \"shape\": -1e300, \"ms\": 1}]}",
         "{\"format\": \"bh-tune-cache\", \"version\": 1, \"version\": 1, \"entries\": []}",
         "{\"format\": \"bh-tune-cache\", \"version\": 1, \"entries\": [1e999]}",
         "[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]",

@@ -17,7 +17,7 @@ ROOT = Path(__file__).resolve().parent.parent
 def test_host_logic_is_clean_under_asan_and_ubsan(tmp_path):
     exe = tmp_path / "host_sanitized"
     cmd = ["g++", "-O1", "-g", "-std=c++17", "-Wall", "-fno-omit-frame-pointer",
-           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fsanitize=address,undefined,float-cast-overflow", "-fno-sanitize-recover=all",
            str(ROOT / "tests" / "host_sanitize_driver.cpp"), "-o", str(exe)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0 and "sanitizer" in res.stderr.lower():

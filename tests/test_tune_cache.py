@@ -58,6 +58,8 @@ def test_round_trip_and_merge(tmp_path, clean):
     json.dumps({"format": "bh-tune-cache", "version": 2, "entries": []}),
     json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(shape=3)]}),
     json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(shape=0x204)]}),
+    json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(shape=-4)]}),
+    json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(shape=-1e300)]}),
     json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(precision="bf16")]}),
     json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [_entry(ms=-1.0)]}),
     json.dumps({"format": "bh-tune-cache", "version": 1, "entries": [{**_entry(), "extra": 1}]}),
