@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <unistd.h>
+
 #include "bh.h"
 #include "bh_common.h"
 #include "bh_host.h"
@@ -874,7 +876,9 @@ static bh_status tune_load_locked(const char *path, bool missing_ok) {
 
 static bh_status tune_save_locked(const char *path) {
     const std::string text = g_tune.to_json();
-    const std::string tmp = std::string(path) + ".tmp";
+    // a per-process temporary name, renamed over the file: concurrent writers do not
+    // interleave, and a reader sees one whole file or the other
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
     FILE *fp = std::fopen(tmp.c_str(), "wb");
     if (!fp) return bh_fail(BH_E_IO, std::string("cannot write tuning cache ") + path);
     const bool ok = std::fwrite(text.data(), 1, text.size(), fp) == text.size();
