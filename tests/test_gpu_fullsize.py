@@ -119,13 +119,18 @@ def test_theta_sweep_4m_sampled(ctx, systems_4m, name):
             del t, r
 
 
-def test_batch_512_forest_sampled(ctx):
+@pytest.fixture(scope="module")
+def batch_512():
+    inst = icgen.batch_instances(512, 6)
+    systems = [icgen.plummer(n, seed) for n, _, seed in inst]
+    return inst, systems, icgen.concat(*systems)
+
+
+def test_batch_512_forest_sampled(ctx, batch_512):
     """512 Plummer instances, N log-uniform in [1024, 262144], theta from {0.4, 0.5, 0.7}, eps = 0.01,
     FP32, one forest; 16 instances stratified by N checked against the oracle, plus two KDK steps
     recorded as a graph against the oracle's own trajectory for the 4 smallest of them."""
-    inst = icgen.batch_instances(512, 6)
-    systems = [icgen.plummer(n, seed) for n, _, seed in inst]
-    cat = icgen.concat(*systems)
+    inst, systems, cat = batch_512
     ns = [n for n, _, _ in inst]
     plist = [bh.params(th, 0.01, precision="fp32") for _, th, _ in inst]
     forest = bh.Forest(ctx, ns, plist, dev(cat.pos), dev(cat.vel), dev(cat.mass))
@@ -150,6 +155,39 @@ def test_batch_512_forest_sampled(ctx):
         # FP32 forces (<= 1e-4 relative, |a| <~ 10 here) move positions by <~ dt^2 * 1e-3 per step
         assert np.abs(pos[offs[k]:offs[k + 1]] - x).max() <= 1e-7
         assert rel_rms(acc[offs[k]:offs[k + 1]], a) <= 2e-6
+
+
+def test_batch_512_forest_20_steps_reanchored(ctx, batch_512):
+    """The batch run as the benchmark times it: autotuned launch shape, one recorded step graph
+    replayed for 20 KDK steps of dt = 1e-3.  After steps 10 and 20 the oracle evaluates the forces
+    from the GPU's own positions (re-anchored: trajectories need not agree bit for bit) on 256
+    sampled targets of 8 instances stratified by N; the forest's accelerations, those of the last
+    evaluation, meet the FP32 gates."""
+    inst, systems, cat = batch_512
+    ns = [n for n, _, _ in inst]
+    plist = [bh.params(th, 0.01, precision="fp32") for _, th, _ in inst]
+    forest = bh.Forest(ctx, ns, plist, dev(cat.pos), dev(cat.vel), dev(cat.mass))
+    forest.autotune()
+    dts = [1e-3] * len(ns)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    order = np.argsort(ns)
+    pick = order[np.linspace(0, len(ns) - 1, 8).astype(int)]
+    rng = np.random.default_rng(23)
+    forest.step_graph(1, dts)   # records the step graph
+    for done, todo in ((10, 9), (20, 10)):
+        print(f"[fullsize] batch 512: steps to {done}", flush=True)
+        forest.step_graph(todo, dts)
+        ctx.sync()
+        pos = forest.pos.cpu().numpy()
+        acc = forest.acc.cpu().numpy()
+        assert np.isfinite(pos).all() and np.isfinite(acc).all()
+        for k in pick:
+            x = pos[offs[k]:offs[k + 1]]
+            tg = np.sort(rng.choice(ns[k], min(256, ns[k]), replace=False)).astype(np.int64)
+            ref = oracle.forces(x, systems[k].mass, theta=inst[k][1], eps=0.01, targets=tg, nthreads=CORES)
+            a = acc[offs[k]:offs[k + 1]][tg]
+            assert rel_rms(a, ref["acc"]) <= 2e-6, (done, k)
+            assert rel_max(a, ref["acc"]) <= 1e-4, (done, k)
 
 
 def test_served_request_matches_oracle(ctx):
