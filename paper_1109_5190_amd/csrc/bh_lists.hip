@@ -175,118 +175,9 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
     const float ty = (float)__dsub_rn(f.spos[3 * (size_t)r + 1], gy);
     const float tz = (float)__dsub_rn(f.spos[3 * (size_t)r + 2], gz);
     const float eps2 = (float)(sd.eps * sd.eps);
-    constexpr bool soft = SOFT;
-
-    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    float sx = 0.f, sy = 0.f, sz = 0.f, sp_ = 0.f;
-    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
-    uint32_t work = 0, qn = 0;
-    auto fold = [&]() {
-        kahan_add(sx, cx, ax); ax = 0.f;
-        kahan_add(sy, cy, ay); ay = 0.f;
-        kahan_add(sz, cz, az); az = 0.f;
-        if (POT) { kahan_add(sp_, cp, ap); ap = 0.f; }
-        work = 0;
-    };
-    auto pair = [&](float px, float py, float pz, float pm) {
-        const float dx = px - tx, dy = py - ty, dz = pz - tz;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-        if (soft || r2 > 0.0f) {
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const float mr = pm * ri;
-            const float w3 = mr * ri * ri;
-            ax = fmaf(w3, dx, ax);
-            ay = fmaf(w3, dy, ay);
-            az = fmaf(w3, dz, az);
-            if (POT) ap -= mr;
-        }
-    };
-    auto pair_batch = [&]() {
-        if (qn == 0) return;
-        if (work + qn > kFlushWork) fold();
-        work += qn;
-        if (!SOFT) {
-            const float tlx = (float)(__dsub_rn(f.spos[3 * (size_t)r], gx) - (double)tx);
-            const float tly = (float)(__dsub_rn(f.spos[3 * (size_t)r + 1], gy) - (double)ty);
-            const float tlz = (float)(__dsub_rn(f.spos[3 * (size_t)r + 2], gz) - (double)tz);
-            for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
-                const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
-                wave_sync();
-                if ((uint32_t)lane < nb) {
-                    const size_t j = L.irank[k0 + lane];
-                    const double ex_ = __dsub_rn(f.spos[3 * j], gx), ey = __dsub_rn(f.spos[3 * j + 1], gy),
-                                 ez = __dsub_rn(f.spos[3 * j + 2], gz);
-                    const float hx = (float)ex_, hy = (float)ey, hz = (float)ez;
-                    L.pst[2 * lane] = make_float4(hx, hy, hz, (float)f.smass[j]);
-                    L.pst[2 * lane + 1] = make_float4((float)(ex_ - (double)hx), (float)(ey - (double)hy),
-                                                      (float)(ez - (double)hz), 0.0f);
-                }
-                wave_sync();
-                for (uint32_t k = 0; k < nb; ++k) {
-                    const uint32_t jq = uni(L.irank[k0 + k]);
-                    const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
-                    if (in_mask(m)) {
-                        const float4 ph = L.pst[2 * k], pl = L.pst[2 * k + 1];
-                        const float dx = (ph.x - tx) + (pl.x - tlx), dy = (ph.y - ty) + (pl.y - tly),
-                                    dz = (ph.z - tz) + (pl.z - tlz);
-                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        if (r2 > 0.0f) {
-                            const float ri = __builtin_amdgcn_rsqf(r2);
-                            const float mr = ph.w * ri;
-                            const float w3 = mr * ri * ri;
-                            ax = fmaf(w3, dx, ax);
-                            ay = fmaf(w3, dy, ay);
-                            az = fmaf(w3, dz, az);
-                            if (POT) ap -= mr;
-                        }
-                    }
-                }
-            }
-            qn = 0;
-            wave_sync();
-            return;
-        }
-        wave_sync();
-        if ((uint32_t)lane < qn) {
-            const size_t j = L.irank[lane];
-            L.pst[lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx), (float)__dsub_rn(f.spos[3 * j + 1], gy),
-                                      (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
-        }
-        wave_sync();
-        for (uint32_t k = 0; k < qn; ++k) {
-            const uint32_t jq = uni(L.irank[k]);
-            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
-            if (in_mask(m)) {
-                const float4 p = L.pst[k];
-                pair(p.x, p.y, p.z, p.w);
-            }
-        }
-        qn = 0;
-        wave_sync();
-    };
-
-    // the walk's leaf pairs: after each stack entry, the queued particles, then the
-    // leaves that did not fit the queue
-    uint32_t nov = 0;
-    auto flush = [&]() {
-        pair_batch();
-        for (uint32_t j = 0; j < nov; ++j) {
-            const uint4 lf = L.ovf[j];
-            const uint32_t first = uni(lf.x), np = uni(lf.y);
-            const uint64_t m = ((uint64_t)uni(lf.w) << 32) | uni(lf.z);
-            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                wave_sync();
-                if ((uint32_t)lane < nb) {
-                    L.irank[lane] = first + b0 + lane;
-                    L.imask[lane] = m;
-                }
-                qn = nb;
-                pair_batch();
-            }
-        }
-        nov = 0;
-    };
+    // the walk's force sums and leaf pairs (after each stack entry, the queued particles,
+    // then the leaves that did not fit the queue)
+    Sums32<false, POT, SOFT> sums{f, L, lane, r, gstart, gx, gy, gz, tx, ty, tz, eps2, 0ull, 0u};
 
     const uint32_t n = uni(ld.count[gi]);
     uint32_t chunk = uni(ld.head[gi]);
@@ -307,23 +198,12 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
             const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.w, k) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.z, k);
             if (a == kListEntry) {
-                if (qn > 56u || nov) flush();   // the previous entry's pairs
-                if (work + b > kFlushWork) fold();
-                work += b;
+                if (sums.qn > 56u || sums.nov) sums.flush();   // the previous entry's pairs
+                if (sums.work + b > kFlushWork) sums.fold();
+                sums.work += b;
             } else if (b & kListLeaf) {
-                const uint32_t np = b & ~kListLeaf;
-                if (qn + np <= 64u) {
-                    wave_sync();
-                    if ((uint32_t)lane < np) {
-                        L.irank[qn + lane] = a + lane;
-                        L.imask[qn + lane] = m;
-                    }
-                    qn += np;
-                } else {
-                    wave_sync();
-                    if (lane == 0) L.ovf[nov] = make_uint4(a, np, (uint32_t)m, (uint32_t)(m >> 32));
-                    ++nov;
-                }
+                wave_sync();
+                sums.queue_leaf(a, b & ~kListLeaf, m);
             } else if (in_mask(m)) {
                 const float4 qa = mst[k];
                 const float dx = qa.x - tx, dy = qa.y - ty, dz = qa.z - tz;
@@ -366,32 +246,32 @@ __global__ void __launch_bounds__(64 * W) k_lists_eval32(ForestDev f, ListDev ld
                             qp = (float)(-0.5 * A64 * r5);
                         }
                     }
-                    ax += qx;
-                    ay += qy;
-                    az += qz;
-                    if (POT) ap += qp;
+                    sums.ax += qx;
+                    sums.ay += qy;
+                    sums.az += qz;
+                    if (POT) sums.ap += qp;
                 }
-                ax = fmaf(w3, dx, ax);
-                ay = fmaf(w3, dy, ay);
-                az = fmaf(w3, dz, az);
-                if (POT) ap -= mr;
+                sums.ax = fmaf(w3, dx, sums.ax);
+                sums.ay = fmaf(w3, dy, sums.ay);
+                sums.az = fmaf(w3, dz, sums.az);
+                if (POT) sums.ap -= mr;
             }
         }
         chunk = uni(ld.next[chunk]);
     }
-    flush();
-    fold();
+    sums.flush();
+    sums.fold();
     if (live) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
         double *accb = seg_base(out.acc, sd.acc, sd, 3);
-        accb[3 * li] = G * ((double)sx - (double)cx);
-        accb[3 * li + 1] = G * ((double)sy - (double)cy);
-        accb[3 * li + 2] = G * ((double)sz - (double)cz);
+        accb[3 * li] = G * ((double)sums.sx - (double)sums.cx);
+        accb[3 * li + 1] = G * ((double)sums.sy - (double)sums.cy);
+        accb[3 * li + 2] = G * ((double)sums.sz - (double)sums.cz);
         if (POT) {
             double *potb = seg_base(out.pot, sd.pot, sd, 1);
-            if (potb) potb[li] = G * ((double)sp_ - (double)cp);
+            if (potb) potb[li] = G * ((double)sums.sp - (double)sums.cp);
         }
     }
 }
@@ -514,45 +394,7 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
     const uint32_t r = gstart + (live ? (uint32_t)lane : 0u);
     const double tx = f.spos[3 * (size_t)r], ty = f.spos[3 * (size_t)r + 1], tz = f.spos[3 * (size_t)r + 2];
     const double eps2 = __dmul_rn(sd.eps, sd.eps);
-    const bool soft = eps2 > 0.0;
-
-    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
-    uint32_t qn = 0;
-    auto pair = [&](double px, double py, double pz, double pm) {
-        const double dx = px - tx, dy = py - ty, dz = pz - tz;
-        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
-        if (soft || r2 > 0.0) {
-            const double ri = rsqrt64(r2);
-            const double mr = pm * ri;
-            const double w3 = mr * ri * ri;
-            ax = fma(w3, dx, ax);
-            ay = fma(w3, dy, ay);
-            az = fma(w3, dz, az);
-            if (POT) ap -= mr;
-        }
-    };
-    auto flush_leaves = [&]() {
-        if (qn == 0) return;
-        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
-            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
-            wave_sync();
-            if ((uint32_t)lane < nb) {
-                const size_t j = L.irank[k0 + lane];
-                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
-            }
-            wave_sync();
-            for (uint32_t k = 0; k < nb; ++k) {
-                const uint32_t jq = uni(L.irank[k0 + k]);
-                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
-                if (in_mask(m)) {
-                    const double4 p = L.pst[k];
-                    pair(p.x, p.y, p.z, p.w);
-                }
-            }
-        }
-        qn = 0;
-        wave_sync();
-    };
+    Sums64<false, POT, WaveLds64<false>> sums{f, L, lane, gstart, tx, ty, tz, eps2, 0ull, 0u};
 
     const uint32_t n = uni(ld.count[gi]);
     uint32_t chunk = uni(ld.head[gi]);
@@ -572,26 +414,7 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mine.z, k);
             if (a == kListEntry) continue;
             if (b & kListLeaf) {
-                const uint32_t np = b & ~kListLeaf;
-                if (np <= 64u) {
-                    if (qn + np > 64u) flush_leaves();
-                    if ((uint32_t)lane < np) {
-                        L.irank[qn + lane] = a + lane;
-                        L.imask[qn + lane] = m;
-                    }
-                    qn += np;
-                } else {
-                    flush_leaves();
-                    for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                        const uint32_t nq = np - b0 < 64u ? np - b0 : 64u;
-                        if ((uint32_t)lane < nq) {
-                            L.irank[lane] = a + b0 + lane;
-                            L.imask[lane] = m;
-                        }
-                        qn = nq;
-                        flush_leaves();
-                    }
-                }
+                sums.queue_leaf(a, b & ~kListLeaf, m);
             } else if (in_mask(m)) {
                 const double4 qa = mst[k];
                 const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
@@ -611,31 +434,31 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
                     const double A = fma(3.0, fma(dx, sdx, fma(dy, sdy, dz * sdz)), -E2 * tr);
                     const double ri5 = ri2 * ri2 * ri;
                     w3 = fma(2.5 * A, ri5 * ri2, w3);
-                    ax = fma(-ri5, fma(3.0, sdx, -tr * dx), ax);
-                    ay = fma(-ri5, fma(3.0, sdy, -tr * dy), ay);
-                    az = fma(-ri5, fma(3.0, sdz, -tr * dz), az);
-                    if (POT) ap -= 0.5 * A * ri5;
+                    sums.ax = fma(-ri5, fma(3.0, sdx, -tr * dx), sums.ax);
+                    sums.ay = fma(-ri5, fma(3.0, sdy, -tr * dy), sums.ay);
+                    sums.az = fma(-ri5, fma(3.0, sdz, -tr * dz), sums.az);
+                    if (POT) sums.ap -= 0.5 * A * ri5;
                 }
-                ax = fma(w3, dx, ax);
-                ay = fma(w3, dy, ay);
-                az = fma(w3, dz, az);
-                if (POT) ap -= mr;
+                sums.ax = fma(w3, dx, sums.ax);
+                sums.ay = fma(w3, dy, sums.ay);
+                sums.az = fma(w3, dz, sums.az);
+                if (POT) sums.ap -= mr;
             }
         }
         chunk = uni(ld.next[chunk]);
     }
-    flush_leaves();
+    sums.flush_leaves();
     if (live) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
         double *accb = seg_base(out.acc, sd.acc, sd, 3);
-        accb[3 * li] = G * ax;
-        accb[3 * li + 1] = G * ay;
-        accb[3 * li + 2] = G * az;
+        accb[3 * li] = G * sums.ax;
+        accb[3 * li + 1] = G * sums.ay;
+        accb[3 * li + 2] = G * sums.az;
         if (POT) {
             double *potb = seg_base(out.pot, sd.pot, sd, 1);
-            if (potb) potb[li] = G * ap;
+            if (potb) potb[li] = G * sums.ap;
         }
     }
 }

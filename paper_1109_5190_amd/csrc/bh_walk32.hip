@@ -57,135 +57,11 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
         }
     const double theta2 = __dmul_rn(theta, theta);
     const float eps2 = (float)(sd.eps * sd.eps);
-    constexpr bool soft = SOFT;
 
-    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;            // partial sums
-    float sx = 0.f, sy = 0.f, sz = 0.f, sp_ = 0.f;           // Kahan sums
-    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;            // Kahan compensations
-    uint32_t nmono = 0, np2p = 0, nvis = 0, nfb = 0;
+    Sums32<STATS, POT, SOFT> sums{f, L, lane, r, gstart, gx, gy, gz, tx, ty, tz, eps2,
+                               STATS ? (uint64_t)st.nn : 0ull, STATS ? sd.start : 0u};
+    uint32_t nmono = 0, nvis = 0, nfb = 0;
     uint32_t wvis = 0, went = 0, wacc = 0, wleaf = 0;         // wave-level counters (uniform)
-    uint64_t h = 0;
-    uint32_t work = 0;   // terms added to the partial sums since the last fold (wave-uniform)
-    uint32_t qn = 0;     // queued leaf particles (wave-uniform)
-    auto fold = [&]() {
-        kahan_add(sx, cx, ax); ax = 0.f;
-        kahan_add(sy, cy, ay); ay = 0.f;
-        kahan_add(sz, cz, az); az = 0.f;
-        if (POT) { kahan_add(sp_, cp, ap); ap = 0.f; }
-        work = 0;
-    };
-    auto pair = [&](float px, float py, float pz, float pm) {
-        const float dx = px - tx, dy = py - ty, dz = pz - tz;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-        if (soft || r2 > 0.0f) {
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const float mr = pm * ri;
-            const float w3 = mr * ri * ri;
-            ax = fmaf(w3, dx, ax);
-            ay = fmaf(w3, dy, ay);
-            az = fmaf(w3, dz, az);
-            if (POT) ap -= mr;
-        }
-    };
-    // queued leaf particles: load and convert lane-parallel, then one pass per particle
-    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
-    auto pair_batch = [&]() {
-        if (qn == 0) return;
-        if (STATS) wwork += qn;
-        if (work + qn > kFlushWork) fold();
-        work += qn;
-        if (!SOFT) {
-            // without softening a pair can be far closer than the group's extent: each side
-            // is split as x - g = hi + lo (FP32 pair), so the difference of a close pair,
-            // (hi_j - hi_i) + (lo_j - lo_i), carries u |d| instead of u |x - g|
-            const float tlx = (float)(__dsub_rn(f.spos[3 * (size_t)r], gx) - (double)tx);
-            const float tly = (float)(__dsub_rn(f.spos[3 * (size_t)r + 1], gy) - (double)ty);
-            const float tlz = (float)(__dsub_rn(f.spos[3 * (size_t)r + 2], gz) - (double)tz);
-            for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
-                const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
-                wave_sync();
-                if ((uint32_t)lane < nb) {
-                    const size_t j = L.irank[k0 + lane];
-                    const double ex_ = __dsub_rn(f.spos[3 * j], gx), ey = __dsub_rn(f.spos[3 * j + 1], gy),
-                                 ez = __dsub_rn(f.spos[3 * j + 2], gz);
-                    const float hx = (float)ex_, hy = (float)ey, hz = (float)ez;
-                    L.pst[2 * lane] = make_float4(hx, hy, hz, (float)f.smass[j]);
-                    L.pst[2 * lane + 1] = make_float4((float)(ex_ - (double)hx), (float)(ey - (double)hy),
-                                                      (float)(ez - (double)hz), 0.0f);
-                }
-                wave_sync();
-                for (uint32_t k = 0; k < nb; ++k) {
-                    const uint32_t jq = uni(L.irank[k0 + k]);
-                    const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
-                    if (in_mask(m)) {
-                        const float4 ph = L.pst[2 * k], pl = L.pst[2 * k + 1];
-                        const float dx = (ph.x - tx) + (pl.x - tlx), dy = (ph.y - ty) + (pl.y - tly),
-                                    dz = (ph.z - tz) + (pl.z - tlz);
-                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        if (r2 > 0.0f) {
-                            const float ri = __builtin_amdgcn_rsqf(r2);
-                            const float mr = ph.w * ri;
-                            const float w3 = mr * ri * ri;
-                            ax = fmaf(w3, dx, ax);
-                            ay = fmaf(w3, dy, ay);
-                            az = fmaf(w3, dz, az);
-                            if (POT) ap -= mr;
-                        }
-                        if (STATS) {
-                            ++np2p;
-                            h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
-                        }
-                    }
-                }
-            }
-            qn = 0;
-            wave_sync();
-            return;
-        }
-        wave_sync();
-        if ((uint32_t)lane < qn) {
-            const size_t j = L.irank[lane];
-            L.pst[lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx), (float)__dsub_rn(f.spos[3 * j + 1], gy),
-                                      (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
-        }
-        wave_sync();
-        for (uint32_t k = 0; k < qn; ++k) {
-            const uint32_t jq = uni(L.irank[k]);
-            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
-            if (in_mask(m)) {
-                const float4 p = L.pst[k];
-                pair(p.x, p.y, p.z, p.w);
-                if (STATS) {
-                    ++np2p;
-                    h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
-                }
-            }
-        }
-        qn = 0;
-        wave_sync();
-    };
-    // Leaf pairs are taken at one point after each stack entry: the queued particles
-    // in queue order, then the leaves that did not fit (64 particles at a time).
-    uint32_t nov = 0;   // leaves in L.ovf (wave-uniform)
-    auto flush = [&]() {
-        pair_batch();
-        for (uint32_t k = 0; k < nov; ++k) {
-            const uint4 lf = L.ovf[k];
-            const uint32_t first = uni(lf.x), np = uni(lf.y);
-            const uint64_t m = ((uint64_t)uni(lf.w) << 32) | uni(lf.z);
-            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                wave_sync();
-                if ((uint32_t)lane < nb) {
-                    L.irank[lane] = first + b0 + lane;
-                    L.imask[lane] = m;
-                }
-                qn = nb;
-                pair_batch();
-            }
-        }
-        nov = 0;
-    };
 
     // Depth-first stack of (first child slot, children, lane mask); the most recent
     // push stays in scalar registers and is the next pop, so only entries pushed
@@ -211,7 +87,7 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
             nch = uni(e.y);
             emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         }
-        if (STATS) wwork += nch;
+        if (STATS) sums.wwork += nch;
         wave_sync();
         if ((uint32_t)lane < nch) {
             const ChildRecs32 cr(f.w32 + link);
@@ -254,8 +130,8 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
             }
         }
         wave_sync();
-        if (work + nch > kFlushWork) fold();
-        work += nch;
+        if (sums.work + nch > kFlushWork) sums.fold();
+        sums.work += nch;
         if (STATS) { wvis += nch; ++went; }
 #pragma unroll
         for (uint32_t c = 0; c < 8; ++c) {
@@ -300,16 +176,7 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
                         // queued; its pairs are taken after this entry
                         const uint32_t np = qcnt & ~kLeafBit;
                         if (STATS) ++wleaf;
-                        if (qn + np <= 64u) {
-                            if ((uint32_t)lane < np) {
-                                L.irank[qn + lane] = qlink + lane;
-                                L.imask[qn + lane] = open;
-                            }
-                            qn += np;
-                        } else {
-                            if (lane == 0) L.ovf[nov] = make_uint4(qlink, np, (uint32_t)open, (uint32_t)(open >> 32));
-                            ++nov;
-                        }
+                        sums.queue_leaf(qlink, np, open);
                     } else {
                         if (pend) {   // the pending entry goes beneath the new one
                             if (sp < kStackMax) {
@@ -374,54 +241,54 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
                             qp = (float)(-0.5 * A64 * r5);
                         }
                     }
-                    ax += qx;
-                    ay += qy;
-                    az += qz;
-                    if (POT) ap += qp;
+                    sums.ax += qx;
+                    sums.ay += qy;
+                    sums.az += qz;
+                    if (POT) sums.ap += qp;
                 }
-                ax = fmaf(w3, dx, ax);
-                ay = fmaf(w3, dy, ay);
-                az = fmaf(w3, dz, az);
-                if (POT) ap -= mr;
+                sums.ax = fmaf(w3, dx, sums.ax);
+                sums.ay = fmaf(w3, dy, sums.ay);
+                sums.az = fmaf(w3, dz, sums.az);
+                if (POT) sums.ap -= mr;
                 if (STATS) {
                     ++nmono;
-                    h += mix64((uint64_t)(L.sc[c].x - st.nbase));
+                    sums.h += mix64((uint64_t)(L.sc[c].x - st.nbase));
                 }
             }
         }
         // room for the next entry's eight children: at most 56 queued particles, no overflow
-        if (qn > 56u || nov) flush();
+        if (sums.qn > 56u || sums.nov) sums.flush();
     }
-    flush();
-    fold();
+    sums.flush();
+    sums.fold();
     const bool own = live && r >= out.wlo && r < out.whi;
-    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)sums.wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
         double *accb = seg_base(out.acc, sd.acc, sd, 3);
         if (accb) {   // null: a counting walk for the checksums only
-            accb[3 * li] = G * ((double)sx - (double)cx);
-            accb[3 * li + 1] = G * ((double)sy - (double)cy);
-            accb[3 * li + 2] = G * ((double)sz - (double)cz);
+            accb[3 * li] = G * ((double)sums.sx - (double)sums.cx);
+            accb[3 * li + 1] = G * ((double)sums.sy - (double)sums.cy);
+            accb[3 * li + 2] = G * ((double)sums.sz - (double)sums.cz);
         }
         if (POT) {
             double *potb = seg_base(out.pot, sd.pot, sd, 1);
-            if (potb) potb[li] = G * ((double)sp_ - (double)cp);
+            if (potb) potb[li] = G * ((double)sums.sp - (double)sums.cp);
         }
         if (STATS) {
             if (out.n_mono) out.n_mono[i] = nmono;
-            if (out.n_p2p) out.n_p2p[i] = np2p;
-            if (out.hash) out.hash[i] = h;
+            if (out.n_p2p) out.n_p2p[i] = sums.np2p;
+            if (out.hash) out.hash[i] = sums.h;
             if (out.work) {   // the group's wavefront work, spread evenly over its bodies
-                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                const uint64_t wg = sums.wwork, k = (uint32_t)lane, c = gd.count;
                 out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
             }
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? sums.np2p : 0);
         unsigned long long v = wave_sum_u(own ? nvis : 0), fb = wave_sum_u(own ? nfb : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);

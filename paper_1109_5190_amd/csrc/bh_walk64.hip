@@ -30,53 +30,9 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
             bhi[d] = f.gbox[6 * (size_t)r + 3 + d];
         }
     const double eps2 = __dmul_rn(sd.eps, sd.eps);
-    const bool soft = eps2 > 0.0;
-
-    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
-    uint32_t nmono = 0, np2p = 0, nvis = 0;
-    uint64_t h = 0;
-    uint32_t qn = 0;
-    auto pair = [&](double px, double py, double pz, double pm) {
-        const double dx = px - tx, dy = py - ty, dz = pz - tz;
-        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
-        if (soft || r2 > 0.0) {
-            const double ri = rsqrt64(r2);
-            const double mr = pm * ri;
-            const double w3 = mr * ri * ri;
-            ax = fma(w3, dx, ax);
-            ay = fma(w3, dy, ay);
-            az = fma(w3, dz, az);
-            if (POT) ap -= mr;
-        }
-    };
-    uint32_t wwork = 0;   // wavefront work: child tests and pair iterations (uniform)
-    auto flush_leaves = [&]() {
-        if (qn == 0) return;
-        if (STATS) wwork += qn;
-        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
-            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
-            wave_sync();
-            if ((uint32_t)lane < nb) {
-                const size_t j = L.irank[k0 + lane];
-                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
-            }
-            wave_sync();
-            for (uint32_t k = 0; k < nb; ++k) {
-                const uint32_t jq = uni(L.irank[k0 + k]);
-                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
-                if (in_mask(m)) {
-                    const double4 p = L.pst[k];
-                    pair(p.x, p.y, p.z, p.w);
-                    if (STATS) {
-                        ++np2p;
-                        h += mix64((uint64_t)st.nn + (uint64_t)(f.idx[jq] - sd.start));
-                    }
-                }
-            }
-        }
-        qn = 0;
-        wave_sync();
-    };
+    Sums64<STATS, POT, WaveLds64<QUAD>> sums{f, L, lane, gstart, tx, ty, tz, eps2,
+                                          STATS ? (uint64_t)st.nn : 0ull, STATS ? sd.start : 0u};
+    uint32_t nmono = 0, nvis = 0;
 
     // Depth-first stack of (first child slot, children, lane mask); the most recent
     // push stays in scalar registers and is the next pop, so only entries pushed
@@ -102,7 +58,7 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
             nch = uni(e.y);
             emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         }
-        if (STATS) wwork += nch;
+        if (STATS) sums.wwork += nch;
         wave_sync();
         if ((uint32_t)lane < nch) {
             const WRec64 *wb = f.w64 + link;   // wave-uniform base, lane offset
@@ -129,26 +85,7 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
                 const uint4 qb = L.sb[c];
                 const uint32_t qlink = uni(qb.x), qcnt = uni(qb.y);
                 if (qcnt & kLeafBit) {
-                    const uint32_t np = qcnt & ~kLeafBit;
-                    if (np <= 64u) {
-                        if (qn + np > 64u) flush_leaves();
-                        if ((uint32_t)lane < np) {
-                            L.irank[qn + lane] = qlink + lane;
-                            L.imask[qn + lane] = open;
-                        }
-                        qn += np;
-                    } else {
-                        flush_leaves();
-                        for (uint32_t b0 = 0; b0 < np; b0 += 64) {
-                            const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
-                            if ((uint32_t)lane < nb) {
-                                L.irank[lane] = qlink + b0 + lane;
-                                L.imask[lane] = open;
-                            }
-                            qn = nb;
-                            flush_leaves();
-                        }
-                    }
+                    sums.queue_leaf(qlink, qcnt & ~kLeafBit, open);
                 } else {
                     if (pend) {   // the pending entry goes beneath the new one
                         if (sp < kStackMax) {
@@ -182,51 +119,51 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
                     const double A = fma(3.0, fma(dx, sdx, fma(dy, sdy, dz * sdz)), -E2 * tr);
                     const double ri5 = ri2 * ri2 * ri;
                     w3 = fma(2.5 * A, ri5 * ri2, w3);
-                    ax = fma(-ri5, fma(3.0, sdx, -tr * dx), ax);
-                    ay = fma(-ri5, fma(3.0, sdy, -tr * dy), ay);
-                    az = fma(-ri5, fma(3.0, sdz, -tr * dz), az);
-                    if (POT) ap -= 0.5 * A * ri5;
+                    sums.ax = fma(-ri5, fma(3.0, sdx, -tr * dx), sums.ax);
+                    sums.ay = fma(-ri5, fma(3.0, sdy, -tr * dy), sums.ay);
+                    sums.az = fma(-ri5, fma(3.0, sdz, -tr * dz), sums.az);
+                    if (POT) sums.ap -= 0.5 * A * ri5;
                 }
-                ax = fma(w3, dx, ax);
-                ay = fma(w3, dy, ay);
-                az = fma(w3, dz, az);
-                if (POT) ap -= mr;
+                sums.ax = fma(w3, dx, sums.ax);
+                sums.ay = fma(w3, dy, sums.ay);
+                sums.az = fma(w3, dz, sums.az);
+                if (POT) sums.ap -= mr;
                 if (STATS) {
                     ++nmono;
-                    h += mix64((uint64_t)(L.sb[c].z - st.nbase));
+                    sums.h += mix64((uint64_t)(L.sb[c].z - st.nbase));
                 }
             }
         }
     }
-    flush_leaves();
+    sums.flush_leaves();
     const bool own = live && r >= out.wlo && r < out.whi;
-    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)wwork;
+    if (STATS && out.gwork && lane == 0) out.gwork[(gstart - sd.start) / kGroup] = (int64_t)sums.wwork;
     if (own) {
         const uint32_t i = f.idx[r];
         const size_t li = i - sd.start;
         const double G = sd.G;
         double *accb = seg_base(out.acc, sd.acc, sd, 3);
         if (accb) {   // null: a counting walk for the checksums only
-            accb[3 * li] = G * ax;
-            accb[3 * li + 1] = G * ay;
-            accb[3 * li + 2] = G * az;
+            accb[3 * li] = G * sums.ax;
+            accb[3 * li + 1] = G * sums.ay;
+            accb[3 * li + 2] = G * sums.az;
         }
         if (POT) {
             double *potb = seg_base(out.pot, sd.pot, sd, 1);
-            if (potb) potb[li] = G * ap;
+            if (potb) potb[li] = G * sums.ap;
         }
         if (STATS) {
             if (out.n_mono) out.n_mono[i] = nmono;
-            if (out.n_p2p) out.n_p2p[i] = np2p;
-            if (out.hash) out.hash[i] = h;
+            if (out.n_p2p) out.n_p2p[i] = sums.np2p;
+            if (out.hash) out.hash[i] = sums.h;
             if (out.work) {   // the group's wavefront work, spread evenly over its bodies
-                const uint64_t wg = wwork, k = (uint32_t)lane, c = gd.count;
+                const uint64_t wg = sums.wwork, k = (uint32_t)lane, c = gd.count;
                 out.work[i] = (int64_t)((wg * (k + 1)) / c - (wg * k) / c);
             }
         }
     }
     if (STATS) {
-        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? np2p : 0);
+        unsigned long long a = wave_sum_u(own ? nmono : 0), b = wave_sum_u(own ? sums.np2p : 0);
         unsigned long long v = wave_sum_u(own ? nvis : 0);
         if (lane == 0) {
             atomicAdd(&f.stats[0], a);

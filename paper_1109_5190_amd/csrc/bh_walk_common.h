@@ -122,6 +122,162 @@ struct ChildRecs32 {
 };
 __device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) { return __hiloint2double((int)hi, (int)lo); }
 
+// Force sums of one lane's body in the FP32 walks and in their list replay: FP32
+// partial sums folded into Kahan-compensated totals after at most kFlushWork
+// terms, and the queue of opened leaves whose particles are taken as pairs after
+// each stack entry (queued particles in queue order, then the leaves that did not
+// fit, 64 particles at a time).  Pair terms are loaded and converted
+// lane-parallel, then added one particle per pass.  STATS: pair counts,
+// interaction-set checksums and the wavefront's pair iterations as well.
+template <bool STATS, bool POT, bool SOFT>
+struct Sums32 {
+    const ForestDev &f;
+    WaveLds32 &L;
+    const int lane;
+    const uint32_t r, gstart;          // this lane's row; the group's first row
+    const double gx, gy, gz;           // the wavefront's reference point g
+    const float tx, ty, tz, eps2;      // this lane's body relative to g; softening^2
+    const uint64_t pair_base;          // STATS: checksum offset of particle terms (node count)
+    const uint32_t seg_start;          // STATS: the simulation's first row
+    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;      // partial sums
+    float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;      // Kahan sums
+    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;      // Kahan compensations
+    uint32_t work = 0;   // terms added to the partial sums since the last fold (wave-uniform)
+    uint32_t qn = 0;     // queued leaf particles (wave-uniform)
+    uint32_t nov = 0;    // leaves in L.ovf (wave-uniform)
+    uint32_t np2p = 0;   // STATS: this body's particle terms
+    uint32_t wwork = 0;  // STATS: the wavefront's child tests and pair iterations (uniform)
+    uint64_t h = 0;      // STATS: this body's interaction-set checksum
+
+    __device__ __forceinline__ void fold() {
+        kahan_add(sx, cx, ax); ax = 0.f;
+        kahan_add(sy, cy, ay); ay = 0.f;
+        kahan_add(sz, cz, az); az = 0.f;
+        if (POT) { kahan_add(sp, cp, ap); ap = 0.f; }
+        work = 0;
+    }
+    __device__ __forceinline__ void pair(float px, float py, float pz, float pm) {
+        const float dx = px - tx, dy = py - ty, dz = pz - tz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+        if (SOFT || r2 > 0.0f) {
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float mr = pm * ri;
+            const float w3 = mr * ri * ri;
+            ax = fmaf(w3, dx, ax);
+            ay = fmaf(w3, dy, ay);
+            az = fmaf(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    }
+    __device__ __forceinline__ void count_pair(uint32_t jq) {
+        if (STATS) {
+            ++np2p;
+            h += mix64(pair_base + (uint64_t)(f.idx[jq] - seg_start));
+        }
+    }
+    __device__ __forceinline__ void pair_batch() {
+        if (qn == 0) return;
+        if (STATS) wwork += qn;
+        if (work + qn > kFlushWork) fold();
+        work += qn;
+        if (!SOFT) {
+            // without softening a pair can be far closer than the group's extent: each side
+            // is split as x - g = hi + lo (FP32 pair), so the difference of a close pair,
+            // (hi_j - hi_i) + (lo_j - lo_i), carries u |d| instead of u |x - g|
+            const float tlx = (float)(__dsub_rn(f.spos[3 * (size_t)r], gx) - (double)tx);
+            const float tly = (float)(__dsub_rn(f.spos[3 * (size_t)r + 1], gy) - (double)ty);
+            const float tlz = (float)(__dsub_rn(f.spos[3 * (size_t)r + 2], gz) - (double)tz);
+            for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+                const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    const size_t j = L.irank[k0 + lane];
+                    const double ex_ = __dsub_rn(f.spos[3 * j], gx), ey = __dsub_rn(f.spos[3 * j + 1], gy),
+                                 ez = __dsub_rn(f.spos[3 * j + 2], gz);
+                    const float hx = (float)ex_, hy = (float)ey, hz = (float)ez;
+                    L.pst[2 * lane] = make_float4(hx, hy, hz, (float)f.smass[j]);
+                    L.pst[2 * lane + 1] = make_float4((float)(ex_ - (double)hx), (float)(ey - (double)hy),
+                                                      (float)(ez - (double)hz), 0.0f);
+                }
+                wave_sync();
+                for (uint32_t k = 0; k < nb; ++k) {
+                    const uint32_t jq = uni(L.irank[k0 + k]);
+                    const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                    if (in_mask(m)) {
+                        const float4 ph = L.pst[2 * k], pl = L.pst[2 * k + 1];
+                        const float dx = (ph.x - tx) + (pl.x - tlx), dy = (ph.y - ty) + (pl.y - tly),
+                                    dz = (ph.z - tz) + (pl.z - tlz);
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (r2 > 0.0f) {
+                            const float ri = __builtin_amdgcn_rsqf(r2);
+                            const float mr = ph.w * ri;
+                            const float w3 = mr * ri * ri;
+                            ax = fmaf(w3, dx, ax);
+                            ay = fmaf(w3, dy, ay);
+                            az = fmaf(w3, dz, az);
+                            if (POT) ap -= mr;
+                        }
+                        count_pair(jq);
+                    }
+                }
+            }
+            qn = 0;
+            wave_sync();
+            return;
+        }
+        wave_sync();
+        if ((uint32_t)lane < qn) {
+            const size_t j = L.irank[lane];
+            L.pst[lane] = make_float4((float)__dsub_rn(f.spos[3 * j], gx), (float)__dsub_rn(f.spos[3 * j + 1], gy),
+                                      (float)__dsub_rn(f.spos[3 * j + 2], gz), (float)f.smass[j]);
+        }
+        wave_sync();
+        for (uint32_t k = 0; k < qn; ++k) {
+            const uint32_t jq = uni(L.irank[k]);
+            const uint64_t m = uni64(L.imask[k]) & ~self_bit(jq, gstart);
+            if (in_mask(m)) {
+                const float4 p = L.pst[k];
+                pair(p.x, p.y, p.z, p.w);
+                count_pair(jq);
+            }
+        }
+        qn = 0;
+        wave_sync();
+    }
+    // an opened leaf of np particles from rank `first`, for the lanes of m
+    __device__ __forceinline__ void queue_leaf(uint32_t first, uint32_t np, uint64_t m) {
+        if (qn + np <= 64u) {
+            if ((uint32_t)lane < np) {
+                L.irank[qn + lane] = first + lane;
+                L.imask[qn + lane] = m;
+            }
+            qn += np;
+        } else {
+            if (lane == 0) L.ovf[nov] = make_uint4(first, np, (uint32_t)m, (uint32_t)(m >> 32));
+            ++nov;
+        }
+    }
+    __device__ __forceinline__ void flush() {
+        pair_batch();
+        for (uint32_t k = 0; k < nov; ++k) {
+            const uint4 lf = L.ovf[k];
+            const uint32_t first = uni(lf.x), np = uni(lf.y);
+            const uint64_t m = ((uint64_t)uni(lf.w) << 32) | uni(lf.z);
+            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                const uint32_t nb = np - b0 < 64u ? np - b0 : 64u;
+                wave_sync();
+                if ((uint32_t)lane < nb) {
+                    L.irank[lane] = first + b0 + lane;
+                    L.imask[lane] = m;
+                }
+                qn = nb;
+                pair_batch();
+            }
+        }
+        nov = 0;
+    }
+};
+
 // Opening thresholds of a child for one wavefront (FP32 walks): E2 > hi accepts,
 // E2 < lo opens, anything between is decided in FP64.  q: the child's centre
 // relative to the wavefront's reference g; rw: bound of |x - g|_inf over its bodies.
@@ -146,6 +302,90 @@ struct WaveLds64 {
     uint32_t irank[64];         // queued leaf particles: rank
     uint64_t imask[64];         //                        lane mask
     double4 pst[32];            //                        position, mass (32 at a time)
+};
+
+// Force sums of one lane's body in the FP64 walks and in their list replay, and the
+// queue of opened leaves whose particles are taken as pairs (32 at a time, loaded
+// lane-parallel).  STATS: pair counts, interaction-set checksums and the
+// wavefront's pair iterations as well.
+template <bool STATS, bool POT, class Lds>
+struct Sums64 {
+    const ForestDev &f;
+    Lds &L;
+    const int lane;
+    const uint32_t gstart;             // the group's first row
+    const double tx, ty, tz, eps2;     // this lane's body; softening^2
+    const uint64_t pair_base;          // STATS: checksum offset of particle terms (node count)
+    const uint32_t seg_start;          // STATS: the simulation's first row
+    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
+    uint32_t qn = 0;     // queued leaf particles (wave-uniform)
+    uint32_t np2p = 0;   // STATS: this body's particle terms
+    uint32_t wwork = 0;  // STATS: the wavefront's child tests and pair iterations (uniform)
+    uint64_t h = 0;      // STATS: this body's interaction-set checksum
+
+    __device__ __forceinline__ void pair(double px, double py, double pz, double pm) {
+        const double dx = px - tx, dy = py - ty, dz = pz - tz;
+        const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+        if (eps2 > 0.0 || r2 > 0.0) {
+            const double ri = rsqrt64(r2);
+            const double mr = pm * ri;
+            const double w3 = mr * ri * ri;
+            ax = fma(w3, dx, ax);
+            ay = fma(w3, dy, ay);
+            az = fma(w3, dz, az);
+            if (POT) ap -= mr;
+        }
+    }
+    __device__ __forceinline__ void flush_leaves() {
+        if (qn == 0) return;
+        if (STATS) wwork += qn;
+        for (uint32_t k0 = 0; k0 < qn; k0 += 32) {
+            const uint32_t nb = qn - k0 < 32u ? qn - k0 : 32u;
+            wave_sync();
+            if ((uint32_t)lane < nb) {
+                const size_t j = L.irank[k0 + lane];
+                L.pst[lane] = make_double4(f.spos[3 * j], f.spos[3 * j + 1], f.spos[3 * j + 2], f.smass[j]);
+            }
+            wave_sync();
+            for (uint32_t k = 0; k < nb; ++k) {
+                const uint32_t jq = uni(L.irank[k0 + k]);
+                const uint64_t m = uni64(L.imask[k0 + k]) & ~self_bit(jq, gstart);
+                if (in_mask(m)) {
+                    const double4 p = L.pst[k];
+                    pair(p.x, p.y, p.z, p.w);
+                    if (STATS) {
+                        ++np2p;
+                        h += mix64(pair_base + (uint64_t)(f.idx[jq] - seg_start));
+                    }
+                }
+            }
+        }
+        qn = 0;
+        wave_sync();
+    }
+    // an opened leaf of np particles from rank `first`, for the lanes of m: queued, after
+    // the queue's particles when it does not fit; a leaf of more than 64 goes alone
+    __device__ __forceinline__ void queue_leaf(uint32_t first, uint32_t np, uint64_t m) {
+        if (np <= 64u) {
+            if (qn + np > 64u) flush_leaves();
+            if ((uint32_t)lane < np) {
+                L.irank[qn + lane] = first + lane;
+                L.imask[qn + lane] = m;
+            }
+            qn += np;
+        } else {
+            flush_leaves();
+            for (uint32_t b0 = 0; b0 < np; b0 += 64) {
+                const uint32_t nq = np - b0 < 64u ? np - b0 : 64u;
+                if ((uint32_t)lane < nq) {
+                    L.irank[lane] = first + b0 + lane;
+                    L.imask[lane] = m;
+                }
+                qn = nq;
+                flush_leaves();
+            }
+        }
+    }
 };
 
 // Group criterion (a variant, not the paper's per-body test): the cube is accepted
