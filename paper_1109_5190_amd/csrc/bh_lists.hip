@@ -92,18 +92,7 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
         const uint32_t link = uni(e.x), nch = uni(e.y);
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
-        if ((uint32_t)lane < nch) {
-            const WRec32 &w = f.w32[link + lane];
-            const float qx = (float)__dsub_rn(w.cx, gx);
-            const float qy = (float)__dsub_rn(w.cy, gy);
-            const float qz = (float)__dsub_rn(w.cz, gz);
-            L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            const float2 band = open_band(w, qx, qy, qz, rw);
-            L.sbh[lane] = band.x;
-            L.sbl[lane] = band.y;
-            L.sl[lane] = make_uint2(w.link, w.cnt);
-            L.sc[lane] = make_uint2(w.gid, w.level);
-        }
+        stage_children32<true, false, false>(f, L, lane, link, nch, gx, gy, gz, rw);
         wave_sync();
         emit(kListEntry, nch, 0);
 #pragma unroll
@@ -118,16 +107,7 @@ __global__ void __launch_bounds__(64 * W) k_lists32(ForestDev f, ListDev ld) {
                 const uint64_t ambm = ballot(!(E2 < L.sbl[c])) & open;
                 if (ambm) {
                     bool ex = false;
-                    if (in_mask(ambm)) {
-                        const WRec32 &wc = f.w32[link + c];
-                        const double cm[3] = {wc.cx, wc.cy, wc.cz};
-                        const double *xp = f.spos + 3 * (size_t)r;
-                        const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
-                                     ez = __dsub_rn(cm[2], xp[2]);
-                        const double ED2 =
-                            __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
-                        ex = f.w32[link + c].r2 < __dmul_rn(__dmul_rn(theta, theta), ED2);
-                    }
+                    if (in_mask(ambm)) ex = exact_accept32(f, link + c, r, theta);
                     accm |= ballot(ex) & ambm;
                     open = emask & ~accm;
                 }
@@ -339,12 +319,7 @@ __global__ void __launch_bounds__(64 * W) k_lists64(ForestDev f, ListDev ld) {
         const uint32_t link = uni(e.x), nch = uni(e.y);
         const uint64_t emask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
         wave_sync();
-        if ((uint32_t)lane < nch) {
-            const WRec64 &w = f.w64[link + lane];
-            L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
-            L.sS[lane] = w.S;
-            L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
-        }
+        stage_children64<false>(f, L, lane, link, nch);
         wave_sync();
 #pragma unroll
         for (uint32_t c = 0; c < 8; ++c) {

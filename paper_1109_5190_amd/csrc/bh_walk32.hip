@@ -70,7 +70,6 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
     bool pend = true;
     uint32_t p_link = sid, p_cnt = 1u;
     uint64_t p_mask = ballot(live);
-    const uint32_t lane_off = (uint32_t)lane * (uint32_t)sizeof(WRec32);   // byte offset of lane c's record
     for (;;) {
         uint32_t link, nch;
         uint64_t emask;
@@ -89,46 +88,7 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
         }
         if (STATS) sums.wwork += nch;
         wave_sync();
-        if ((uint32_t)lane < nch) {
-            const ChildRecs32 cr(f.w32 + link);
-            const v4u32 r0 = cr.q(lane_off, 0), r1 = cr.q(lane_off, 1), r2q = cr.q(lane_off, 2);
-            WRec32 w;
-            w.cx = as_f64(r0.x, r0.y);
-            w.cy = as_f64(r0.z, r0.w);
-            w.cz = as_f64(r1.x, r1.y);
-            w.m = __uint_as_float(r1.z);
-            w.Sh = __uint_as_float(r1.w);
-            w.band0 = __uint_as_float(r2q.x);
-            w.band1 = __uint_as_float(r2q.y);
-            w.link = r2q.z;
-            w.cnt = r2q.w;
-            if (STATS || GROUP) {
-                const v4u32 r3 = cr.q(lane_off, 3);
-                w.gid = r3.x;
-                w.level = r3.y;
-                w.r2 = as_f64(r3.z, r3.w);
-            }
-            const float qx = (float)__dsub_rn(w.cx, gx);
-            const float qy = (float)__dsub_rn(w.cy, gy);
-            const float qz = (float)__dsub_rn(w.cz, gz);
-            L.sa[lane] = make_float4(qx, qy, qz, w.m);
-            if (GROUP) {
-                L.x.g.cx[lane] = w.cx;
-                L.x.g.cy[lane] = w.cy;
-                L.x.g.cz[lane] = w.cz;
-                L.x.g.r2[lane] = w.r2;
-            } else {
-                const float2 band = open_band(w, qx, qy, qz, rw);
-                L.sbh[lane] = band.x;
-                L.sbl[lane] = band.y;
-            }
-            L.sl[lane] = make_uint2(w.link, w.cnt);
-            if (STATS) L.sc[lane] = make_uint2(w.gid, w.level);
-            if (QUAD) {
-                L.x.q.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
-                L.x.q.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
-            }
-        }
+        stage_children32<STATS, QUAD, GROUP>(f, L, lane, link, nch, gx, gy, gz, rw);
         wave_sync();
         if (sums.work + nch > kFlushWork) sums.fold();
         sums.work += nch;
@@ -156,14 +116,7 @@ __device__ __forceinline__ void walk32_group(const ForestDev &f, const WalkOut &
                     // within the FP32 rounding bound of the threshold: decide exactly in FP64
                     bool ex = false;
                     if (in_mask(ambm)) {
-                        const WRec32 &wc = f.w32[link + c];
-                        const double cm[3] = {wc.cx, wc.cy, wc.cz};
-                        const double *xp = f.spos + 3 * (size_t)r;
-                        const double ex_ = __dsub_rn(cm[0], xp[0]), ey = __dsub_rn(cm[1], xp[1]),
-                                     ez = __dsub_rn(cm[2], xp[2]);
-                        const double ED2 =
-                            __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
-                        ex = f.w32[link + c].r2 < __dmul_rn(__dmul_rn(theta, theta), ED2);
+                        ex = exact_accept32(f, link + c, r, theta);
                         if (STATS) ++nfb;
                     }
                     accm |= ballot(ex) & ambm;

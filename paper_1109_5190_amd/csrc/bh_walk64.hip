@@ -41,7 +41,6 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
     bool pend = true;
     uint32_t p_link = sid, p_cnt = 1u;
     uint64_t p_mask = ballot(live);
-    const size_t lane_off = (size_t)lane;
     for (;;) {
         uint32_t link, nch;
         uint64_t emask;
@@ -60,15 +59,7 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
         }
         if (STATS) sums.wwork += nch;
         wave_sync();
-        if ((uint32_t)lane < nch) {
-            const WRec64 *wb = f.w64 + link;   // wave-uniform base, lane offset
-            const WRec64 &w = wb[lane_off];
-            L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
-            L.sS[lane] = w.S;
-            L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
-            if (QUAD)
-                for (int k = 0; k < 6; ++k) L.sq[6 * lane + k] = f.q64[6 * (size_t)(link + lane) + k];
-        }
+        stage_children64<QUAD>(f, L, lane, link, nch);
         wave_sync();
 #pragma unroll
         for (uint32_t c = 0; c < 8; ++c) {

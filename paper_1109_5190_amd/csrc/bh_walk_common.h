@@ -291,6 +291,68 @@ __device__ __forceinline__ float2 open_band(const WRec32 &w, float qx, float qy,
     return make_float2(fmaf(B, 1.0f + 4.0f * kU32, w.Sh), fmaf(B, -(1.0f + 4.0f * kU32), w.Sh * (1.0f - 20.0f * kU32)));
 }
 
+// Stages the children of a stack entry (at most 8, consecutive walk slots from
+// `link`) in LDS, lane c for child c: centre relative to the wavefront's reference
+// point g, mass, link and count, and per variant the FP32 band edges (per-body
+// test), the FP64 centre and r^2 (group criterion), node id and level (IDS), the
+// second moments (QUAD).
+template <bool IDS, bool QUAD, bool GROUP>
+__device__ __forceinline__ void stage_children32(const ForestDev &f, WaveLds32 &L, int lane, uint32_t link,
+                                                 uint32_t nch, double gx, double gy, double gz, float rw) {
+    if ((uint32_t)lane < nch) {
+        const ChildRecs32 cr(f.w32 + link);
+        const uint32_t lane_off = (uint32_t)lane * (uint32_t)sizeof(WRec32);   // byte offset of lane c's record
+        const v4u32 r0 = cr.q(lane_off, 0), r1 = cr.q(lane_off, 1), r2q = cr.q(lane_off, 2);
+        WRec32 w;
+        w.cx = as_f64(r0.x, r0.y);
+        w.cy = as_f64(r0.z, r0.w);
+        w.cz = as_f64(r1.x, r1.y);
+        w.m = __uint_as_float(r1.z);
+        w.Sh = __uint_as_float(r1.w);
+        w.band0 = __uint_as_float(r2q.x);
+        w.band1 = __uint_as_float(r2q.y);
+        w.link = r2q.z;
+        w.cnt = r2q.w;
+        if (IDS || GROUP) {
+            const v4u32 r3 = cr.q(lane_off, 3);
+            w.gid = r3.x;
+            w.level = r3.y;
+            w.r2 = as_f64(r3.z, r3.w);
+        }
+        const float qx = (float)__dsub_rn(w.cx, gx);
+        const float qy = (float)__dsub_rn(w.cy, gy);
+        const float qz = (float)__dsub_rn(w.cz, gz);
+        L.sa[lane] = make_float4(qx, qy, qz, w.m);
+        if (GROUP) {
+            L.x.g.cx[lane] = w.cx;
+            L.x.g.cy[lane] = w.cy;
+            L.x.g.cz[lane] = w.cz;
+            L.x.g.r2[lane] = w.r2;
+        } else {
+            const float2 band = open_band(w, qx, qy, qz, rw);
+            L.sbh[lane] = band.x;
+            L.sbl[lane] = band.y;
+        }
+        L.sl[lane] = make_uint2(w.link, w.cnt);
+        if (IDS) L.sc[lane] = make_uint2(w.gid, w.level);
+        if (QUAD) {
+            L.x.q.sq0[lane] = f.q32[2 * (size_t)(link + lane)];
+            L.x.q.sq1[lane] = f.q32[2 * (size_t)(link + lane) + 1];
+        }
+    }
+}
+
+// The opening test of the cube at walk slot `slot` for the body of sorted row r,
+// decided exactly in FP64 as the oracle evaluates it (lanes whose FP32 distance lies
+// within the rounding band of the threshold).
+__device__ __forceinline__ bool exact_accept32(const ForestDev &f, uint32_t slot, uint32_t r, double theta) {
+    const WRec32 &wc = f.w32[slot];
+    const double *xp = f.spos + 3 * (size_t)r;
+    const double ex_ = __dsub_rn(wc.cx, xp[0]), ey = __dsub_rn(wc.cy, xp[1]), ez = __dsub_rn(wc.cz, xp[2]);
+    const double ED2 = __dadd_rn(__dadd_rn(__dmul_rn(ex_, ex_), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
+    return wc.r2 < __dmul_rn(__dmul_rn(theta, theta), ED2);
+}
+
 
 template <bool QUAD>
 struct WaveLds64 {
@@ -303,6 +365,22 @@ struct WaveLds64 {
     uint64_t imask[64];         //                        lane mask
     double4 pst[32];            //                        position, mass (32 at a time)
 };
+
+// Stages the children of a stack entry (FP64 walks), lane c for child c: centre and
+// mass, r^2 of the opening test, link, count, node id and level, and (QUAD) the
+// second moments.
+template <bool QUAD, class Lds>
+__device__ __forceinline__ void stage_children64(const ForestDev &f, Lds &L, int lane, uint32_t link, uint32_t nch) {
+    if ((uint32_t)lane < nch) {
+        const WRec64 *wb = f.w64 + link;   // wave-uniform base, lane offset
+        const WRec64 &w = wb[lane];
+        L.sa[lane] = make_double4(w.x, w.y, w.z, w.m);
+        L.sS[lane] = w.S;
+        L.sb[lane] = make_uint4(w.link, w.cnt, w.gid, w.level);
+        if (QUAD)
+            for (int k = 0; k < 6; ++k) L.sq[6 * lane + k] = f.q64[6 * (size_t)(link + lane) + k];
+    }
+}
 
 // Force sums of one lane's body in the FP64 walks and in their list replay, and the
 // queue of opened leaves whose particles are taken as pairs (32 at a time, loaded
