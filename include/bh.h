@@ -451,8 +451,10 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
 bh_status bh_server_submit(bh_server *s, const bh_request *req, uint64_t *id);
 /* Thread-safe.  BH_E_BUSY while queued or running (res is still filled). */
 bh_status bh_server_poll(bh_server *s, uint64_t id, bh_result *res);
-/* Copy a finished request's final state into caller device memory (n x 3
- * each, nullable) and release it. */
+/* Copy a finished request's final state into caller memory (n x 3 each,
+ * nullable; device or host) and release it.  SYNC on the server's copy stream
+ * only: it does not wait for the iteration in flight.  Thread-safe; must not
+ * overlap bh_server_destroy. */
 bh_status bh_server_fetch(bh_server *s, uint64_t id, double *pos, double *vel);
 bh_status bh_server_cancel(bh_server *s, uint64_t id);
 /* Seconds on the server clock (same clock as bh_result times). */

@@ -520,6 +520,8 @@ class Server:
         torch = _torch()
         pos = torch.empty((n, 3), dtype=torch.float64, device=self.ctx.device)
         vel = torch.empty((n, 3), dtype=torch.float64, device=self.ctx.device)
+        # the copies run on the server's own stream: torch's pending work on these blocks first
+        torch.cuda.current_stream(pos.device).synchronize()
         _check(lib().bh_server_fetch(self.h, C.c_uint64(rid), _ptr(pos), _ptr(vel)))
         return pos, vel
 

@@ -45,7 +45,7 @@ struct Req {
     int steps_done = 0;
     double t_submit = 0, t_admit = 0, t_done = 0, K = 0, W = 0;
     size_t off = 0, bytes = 0;
-    bool has_mem = false, fresh = false, cancel = false;
+    bool has_mem = false, fresh = false, cancel = false, fetching = false;
     double *pos = nullptr, *vel = nullptr, *acc = nullptr, *mass = nullptr, *pot = nullptr;
 };
 
@@ -56,6 +56,7 @@ size_t state_bytes(int64_t n) { return align256((size_t)n * 11 * sizeof(double))
 struct bh_server {
     bh_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t fetch_stream = nullptr;   // copies of finished requests, apart from the iterations
     bh_ctx sctx;                 // the server's own context (its stream)
     char *arena = nullptr;
     size_t arena_bytes = 0, ws_bytes = 0;
@@ -280,7 +281,9 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     sv->mem.init(sv->ws_bytes + scratch_bytes, arena_bytes - sv->ws_bytes - scratch_bytes);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->fetch_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        if (sv->stream) (void)hipStreamDestroy(sv->stream);
         delete sv;
         return bh_fail(BH_E_DEVICE, std::string("stream creation: ") + hipGetErrorString(e));
     }
@@ -291,6 +294,7 @@ bh_status bh_server_create(bh_ctx *ctx, void *arena, size_t arena_bytes, int32_t
     if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(sv->stream);
+        (void)hipStreamDestroy(sv->fetch_stream);
         delete sv;
         return bh_fail(BH_E_DEVICE, std::string("server init: ") + hipGetErrorString(e));
     }
@@ -346,18 +350,30 @@ bh_status bh_server_poll(bh_server *sv, uint64_t id, bh_result *res) {
 
 bh_status bh_server_fetch(bh_server *sv, uint64_t id, double *pos, double *vel) {
     if (!sv) return bh_fail(BH_E_INVAL, "NULL argument");
-    std::unique_lock<std::mutex> lk(sv->mu);
-    auto it = sv->reqs.find(id);
-    if (it == sv->reqs.end()) return bh_fail(BH_E_NOTFOUND, "unknown request id");
-    Req &q = it->second;
-    if (q.state == kQueued || q.state == kRunning) return bh_fail(BH_E_BUSY, "request not finished");
-    if (q.state != kDone) return bh_fail(BH_E_INVAL, "request did not complete");
-    if (!q.has_mem) return bh_fail(BH_E_INVAL, "request state was released (or already fetched)");
-    const size_t bytes3 = sizeof(double) * 3 * (size_t)q.r.n;
+    const double *src_pos = nullptr, *src_vel = nullptr;
+    size_t bytes3 = 0;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(id);
+        if (it == sv->reqs.end()) return bh_fail(BH_E_NOTFOUND, "unknown request id");
+        Req &q = it->second;
+        if (q.state == kQueued || q.state == kRunning) return bh_fail(BH_E_BUSY, "request not finished");
+        if (q.state != kDone) return bh_fail(BH_E_INVAL, "request did not complete");
+        if (!q.has_mem || q.fetching) return bh_fail(BH_E_INVAL, "request state was released (or already fetched)");
+        q.fetching = true;   // the state stays allocated until the copies are done
+        src_pos = q.pos;
+        src_vel = q.vel;
+        bytes3 = sizeof(double) * 3 * (size_t)q.r.n;
+    }
+    // a finished request's state is written by no later iteration: copy it on a stream of
+    // its own, without waiting for the iteration in flight and without holding the lock
     hipError_t e = hipSuccess;
-    if (pos) e = hipMemcpyAsync(pos, q.pos, bytes3, hipMemcpyDefault, sv->stream);
-    if (e == hipSuccess && vel) e = hipMemcpyAsync(vel, q.vel, bytes3, hipMemcpyDefault, sv->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+    if (pos) e = hipMemcpyAsync(pos, src_pos, bytes3, hipMemcpyDefault, sv->fetch_stream);
+    if (e == hipSuccess && vel) e = hipMemcpyAsync(vel, src_vel, bytes3, hipMemcpyDefault, sv->fetch_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sv->fetch_stream);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    Req &q = sv->reqs[id];
+    q.fetching = false;
     if (e != hipSuccess) return bh_fail(BH_E_DEVICE, std::string("fetch copy: ") + hipGetErrorString(e));
     sv->mem.release(q.off, q.bytes);
     q.has_mem = false;
@@ -388,6 +404,8 @@ bh_status bh_server_destroy(bh_server *sv) {
     if (sv->th.joinable()) sv->th.join();
     (void)hipStreamSynchronize(sv->stream);
     (void)hipStreamDestroy(sv->stream);
+    (void)hipStreamSynchronize(sv->fetch_stream);
+    (void)hipStreamDestroy(sv->fetch_stream);
     delete sv;
     return BH_OK;
 }

@@ -153,3 +153,25 @@ def test_options_alone_equal_mix_and_plain_simulation(ctx):
         sim.step(steps, 1e-3)
         ctx.sync()
         assert torch.equal(pos, alone[k][0]) and torch.equal(vel, alone[k][1]), k
+
+
+def test_fetch_while_another_request_runs(ctx):
+    """A finished request is fetched while a long one is still resident: the copy does not wait
+    for the long request, and the fetched state equals the same request served alone."""
+    sv = bh.Server(ctx, 2 * GiB, max_slots=8, max_resident=1 << 20)
+    req = (3000, 3, 0, 301, 0.5, "fp32")
+    rid = submit(sv, req)
+    assert wait(sv, rid)["state"] == "done"
+    ref_pos, ref_vel = sv.fetch(rid, req[0])
+    long_id = sv.submit(200000, 400, 1, 302, bh.params(0.5, 0.01, precision="fp64"), 1e-4)
+    rid2 = submit(sv, req)
+    assert wait(sv, rid2)["state"] == "done"
+    pos, vel = sv.fetch(rid2, req[0])
+    assert sv.poll(long_id)["state"] == "running"
+    assert torch.equal(pos, ref_pos) and torch.equal(vel, ref_vel)
+    with pytest.raises(bh.BHError):
+        sv.fetch(rid2, req[0])   # released by the first fetch
+    sv.cancel(long_id)
+    assert wait(sv, long_id, timeout=120.0)["state"] == "cancelled"
+    del sv
+
