@@ -26,7 +26,10 @@
  *  - Memory: the CALLER owns all device memory: inputs, outputs, workspaces
  *    and the server arena.  The library sub-allocates inside the workspace it
  *    is given and never frees caller memory.  Handles (bh_ctx, bh_tree,
- *    bh_sim, bh_forest, bh_server) are small host objects.
+ *    bh_sim, bh_forest, bh_server) are small host objects.  A tree,
+ *    simulation or forest belongs to the context it was created on: calls
+ *    that pass another context are refused (BH_E_INVAL), and so are calls on
+ *    a handle whose context was destroyed (only its free/destroy is allowed).
  *  - Ordering: calls are asynchronous on the context's HIP stream; a call
  *    returns once its work is enqueued.  Outputs are valid after the stream
  *    is synchronised (bh_ctx_sync).  Calls marked SYNC synchronise the stream

@@ -430,6 +430,7 @@ bh_status bh_build(bh_ctx *ctx, int64_t n, const double *pos, const double *mass
 
 bh_status bh_rebuild(bh_ctx *ctx, bh_tree *t, const double *pos, const double *mass) {
     if (!ctx || !t || !pos || !mass) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     t->pos = pos;
     t->mass = mass;
     t->upward_done = false;
@@ -440,6 +441,7 @@ bh_status bh_rebuild(bh_ctx *ctx, bh_tree *t, const double *pos, const double *m
 
 bh_status bh_upward(bh_ctx *ctx, bh_tree *t) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     HIPCHK(launch_upward(t->F.dev, ctx->stream));
     t->upward_done = true;
     t->lists_buf = nullptr;
@@ -480,6 +482,7 @@ static_assert(sizeof(bh_list_entry) == bh_host::kListEntryBytes && kListParts ==
 
 bh_status bh_lists_build(bh_ctx *ctx, bh_tree *t, void *buf, size_t bytes, size_t *bytes_needed) {
     if (!ctx || !t || !buf) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (reinterpret_cast<uintptr_t>(buf) % 256) return bh_fail(BH_E_INVAL, "list buffer must be 256-byte aligned");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_lists_build");
     bh_status st = lists_supported(t);
@@ -517,6 +520,7 @@ bh_status bh_lists_build(bh_ctx *ctx, bh_tree *t, void *buf, size_t bytes, size_
 
 bh_status bh_lists_forces(bh_ctx *ctx, bh_tree *t, const void *buf, double *acc, double *pot) {
     if (!ctx || !t || !buf || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!t->lists_buf || t->lists_buf != buf)
         return bh_fail(BH_E_INVAL, "no interaction lists of the current tree in this buffer");
     const ListDev ld = list_dev(const_cast<void *>(buf), t->F.dev.ngroups, t->lists_chunks);
@@ -526,6 +530,7 @@ bh_status bh_lists_forces(bh_ctx *ctx, bh_tree *t, const void *buf, double *acc,
 
 bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces");
     HIPCHK(launch_walk(t->F.dev, false, pot != nullptr, acc, pot, nullptr, nullptr, nullptr, ctx->stream,
                        t->F.walk_shape));
@@ -535,6 +540,7 @@ bh_status bh_forces(bh_ctx *ctx, bh_tree *t, double *acc, double *pot) {
 bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int64_t *n_mono, int64_t *n_p2p,
                           uint64_t *hash, bh_stats *totals) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_stats");
     EventPair ev;
     HIPCHK(hipEventCreate(&ev.a));
@@ -567,6 +573,7 @@ bh_status bh_forces_stats(bh_ctx *ctx, bh_tree *t, double *acc, double *pot, int
 bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count, double *acc, double *pot,
                           int64_t *n_mono, int64_t *n_p2p, int64_t *work, int64_t *group_work) {
     if (!ctx || !t || !acc) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "bh_upward must run before bh_forces_range");
     const int64_t n = t->F.dev.ntot;
     if (first < 0 || count < 0 || first > n || count > n - first)
@@ -590,6 +597,7 @@ bh_status bh_forces_range(bh_ctx *ctx, bh_tree *t, int64_t first, int64_t count,
 bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *t, const int64_t *cost_a, const int64_t *cost_b, int32_t G,
                           int64_t *bounds) {
     if (!ctx || !t || !bounds) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (G < 1 || G > 65536) return bh_fail(BH_E_INVAL, "G must be in [1, 65536]");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "the tree must be built (bh_upward) before bh_shard_bounds");
     HIPCHK(launch_shard_bounds(t->F.dev, t->F.dev.ntot, cost_a, cost_b, nullptr, (uint32_t)G, bounds, ctx->stream));
@@ -598,6 +606,7 @@ bh_status bh_shard_bounds(bh_ctx *ctx, bh_tree *t, const int64_t *cost_a, const 
 
 bh_status bh_shard_bounds_groups(bh_ctx *ctx, bh_tree *t, const int64_t *group_work, int32_t G, int64_t *bounds) {
     if (!ctx || !t || !group_work || !bounds) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (G < 1 || G > 65536) return bh_fail(BH_E_INVAL, "G must be in [1, 65536]");
     if (!t->upward_done) return bh_fail(BH_E_INVAL, "the tree must be built (bh_upward) before bh_shard_bounds_groups");
     HIPCHK(launch_shard_bounds(t->F.dev, t->F.dev.ntot, nullptr, nullptr, group_work, (uint32_t)G, bounds,
@@ -607,6 +616,7 @@ bh_status bh_shard_bounds_groups(bh_ctx *ctx, bh_tree *t, const int64_t *group_w
 
 bh_status bh_tree_info(bh_ctx *ctx, bh_tree *t, int64_t *n_nodes, double lo[3], int32_t *k) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     SegState s;
     HIPCHK(hipMemcpyAsync(&s, t->F.dev.st, sizeof(SegState), hipMemcpyDeviceToHost, ctx->stream));
     bh_status st = bh_forest_check_err(t->F);
@@ -621,6 +631,7 @@ bh_status bh_tree_export(bh_ctx *ctx, bh_tree *t, uint64_t *keys, uint32_t *perm
                          uint32_t *count, int32_t *parent, double *M, double *com, int64_t *n_nodes,
                          uint64_t *isect_hash) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if ((M || com || isect_hash) && !t->upward_done)
         return bh_fail(BH_E_INVAL, "bh_upward must run before exporting M, com or the checksums");
     HIPCHK(launch_export(t->F.dev, 0, keys, perm, level, first, count, parent, M, com, ctx->stream));
@@ -671,6 +682,7 @@ bh_status bh_sim_create(bh_ctx *ctx, int64_t n, double *pos, double *vel, const 
 
 bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
     if (!ctx || !sm) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (sm->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (nsteps < 0 || !std::isfinite(dt)) return bh_fail(BH_E_INVAL, "nsteps must be >= 0 and dt finite");
     if (sm->F.seg[0].dt != dt) {
         sm->F.seg[0].dt = dt;
@@ -687,6 +699,7 @@ bh_status bh_step(bh_ctx *ctx, bh_sim *sm, int32_t nsteps, double dt) {
 
 bh_status bh_energy(bh_ctx *ctx, bh_sim *sm, double out_KW[2]) {
     if (!ctx || !sm || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (sm->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     bh_status st = bh_forest_eval(sm->F, sm->pos, sm->mass, sm->acc, sm->F.dev.pot, true, nullptr);
     if (st != BH_OK) return st;
     sm->have_acc = true;
@@ -757,6 +770,7 @@ static bh_status forest_set_dt(bh_forest *fo, const double *dt) {
 
 bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const double *dt) {
     if (!ctx || !fo || !dt) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (nsteps < 0) return bh_fail(BH_E_INVAL, "nsteps must be >= 0");
     bh_status st = forest_set_dt(fo, dt);
     if (st != BH_OK) return st;
@@ -770,6 +784,7 @@ bh_status bh_forest_step(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const doubl
 
 bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *fo, double *pot) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, pot, pot != nullptr, nullptr);
     if (st == BH_OK) fo->have_acc = true;
     return st;
@@ -777,6 +792,7 @@ bh_status bh_forest_forces(bh_ctx *ctx, bh_forest *fo, double *pot) {
 
 bh_status bh_forest_step_graph(bh_ctx *ctx, bh_forest *fo, int32_t nsteps, const double *dt) {
     if (!ctx || !fo || !dt) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (nsteps < 0) return bh_fail(BH_E_INVAL, "nsteps must be >= 0");
     bh_status st = forest_set_dt(fo, dt);
     if (st != BH_OK) return st;
@@ -924,6 +940,7 @@ static void forest_take_shape(bh_forest *fo, int shape) {
 
 bh_status bh_tree_set_walk_shape(bh_ctx *ctx, bh_tree *t, int32_t shape) {
     if (!ctx || !t) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (t->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
     t->F.walk_shape = shape;
     return BH_OK;
@@ -931,6 +948,7 @@ bh_status bh_tree_set_walk_shape(bh_ctx *ctx, bh_tree *t, int32_t shape) {
 
 bh_status bh_sim_set_walk_shape(bh_ctx *ctx, bh_sim *sm, int32_t shape) {
     if (!ctx || !sm) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (sm->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
     sm->F.walk_shape = shape;
     return BH_OK;
@@ -938,6 +956,7 @@ bh_status bh_sim_set_walk_shape(bh_ctx *ctx, bh_sim *sm, int32_t shape) {
 
 bh_status bh_forest_set_walk_shape(bh_ctx *ctx, bh_forest *fo, int32_t shape) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (!valid_walk_shape(shape)) return bh_fail(BH_E_INVAL, "shape must be 1, 2, 4 or 8, optionally | BH_WALK_PERSISTENT");
     forest_take_shape(fo, shape);
     return BH_OK;
@@ -945,6 +964,7 @@ bh_status bh_forest_set_walk_shape(bh_ctx *ctx, bh_forest *fo, int32_t shape) {
 
 bh_status bh_forest_autotune(bh_ctx *ctx, bh_forest *fo, uint32_t flags, int32_t *shape_out, double *ms_out) {
     if (!ctx || !fo) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     if (flags & ~BH_TUNE_CACHED) return bh_fail(BH_E_INVAL, "unknown bits in flags");
     hipStream_t s = ctx->stream;
     ForestHost &F = fo->F;
@@ -1021,6 +1041,7 @@ bh_status bh_forest_destroy(bh_ctx *ctx, bh_forest *fo) {
 
 bh_status bh_forest_energy(bh_ctx *ctx, bh_forest *fo, double *out_KW) {
     if (!ctx || !fo || !out_KW) return bh_fail(BH_E_INVAL, "NULL argument");
+    if (fo->F.ctx != ctx) return bh_fail(BH_E_INVAL, "handle created on another context, or its context was destroyed");
     bh_status st = bh_forest_eval(fo->F, fo->pos, fo->mass, fo->acc, fo->F.dev.pot, true, nullptr);
     if (st != BH_OK) return st;
     fo->have_acc = true;

@@ -165,3 +165,25 @@ def test_ic_generate_needs_its_workspace(ctx):
     assert L.bh_ic_generate(*args, bh._ptr(ws), nb) == bh.OK
     ctx.sync()
     assert torch.isfinite(pos).all() and torch.isfinite(vel).all()
+
+
+def test_handles_refuse_another_context(ctx):
+    """A tree, simulation or forest belongs to the context it was created on: a call that passes
+    another context is refused (BH_E_INVAL) and changes nothing; its own context still works."""
+    s = icgen.plummer(2000, 15)
+    p = bh.params(0.5, 0.01, precision="fp32")
+    t = bh.Tree(ctx, dev(s.pos), dev(s.mass), p).upward()
+    a = t.forces().clone()
+    other = bh.Context(0)
+    acc = torch.zeros_like(a)
+    st = bh.lib().bh_forces(other.h, t.h, bh._ptr(acc), None)
+    assert st == bh.E_INVAL
+    assert "another context" in bh.lib().bh_last_error().decode()
+    assert torch.count_nonzero(acc) == 0
+    sim = bh.Sim(ctx, dev(s.pos), dev(s.vel), dev(s.mass), p)
+    assert bh.lib().bh_step(other.h, sim.h, 1, bh.C.c_double(1e-3)) == bh.E_INVAL
+    sim.step(1, 1e-3)
+    ctx.sync()
+    assert torch.equal(t.forces(), a)
+    other.sync()
+
