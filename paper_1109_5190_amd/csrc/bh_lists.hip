@@ -395,11 +395,13 @@ __global__ void __launch_bounds__(256) k_lists_eval64(ForestDev f, ListDev ld, W
                 const double dx = __dsub_rn(qa.x, tx), dy = __dsub_rn(qa.y, ty), dz = __dsub_rn(qa.z, tz);
                 const double D2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
                 const double E2 = D2 + eps2;
-                const double ri = rsqrt64(E2);
-                const double mr = qa.w * ri;
-                const double ri2 = ri * ri;
-                double w3 = mr * ri2;
+                double w3, mr = 0.0;
+                if (!QUAD) mono64<POT>(E2, qa.w, w3, mr);
                 if (QUAD) {
+                    const double ri = rsqrt64(E2);
+                    const double ri2 = ri * ri;
+                    mr = qa.w * ri;
+                    w3 = mr * ri2;
                     // the walk's quadrupole term, from the moments of walk slot a
                     const double *q = f.q64 + 6 * (size_t)a;
                     const double sdx = fma(q[0], dx, fma(q[3], dy, q[4] * dz));

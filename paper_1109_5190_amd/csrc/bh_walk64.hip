@@ -97,11 +97,13 @@ __device__ __forceinline__ void walk64_group(const ForestDev &f, const WalkOut &
                 // softened monopole, executed by the accepting lanes only
                 __asm__ volatile("");
                 const double E2 = D2 + eps2;
-                const double ri = rsqrt64(E2);
-                const double mr = qa.w * ri;
-                const double ri2 = ri * ri;
-                double w3 = mr * ri2;
+                double w3, mr = 0.0;
+                if (!QUAD) mono64<POT>(E2, qa.w, w3, mr);
                 if (QUAD) {
+                    const double ri = rsqrt64(E2);
+                    const double ri2 = ri * ri;
+                    mr = qa.w * ri;
+                    w3 = mr * ri2;
                     const double *q = &L.sq[6 * c];
                     const double sdx = fma(q[0], dx, fma(q[3], dy, q[4] * dz));
                     const double sdy = fma(q[3], dx, fma(q[1], dy, q[5] * dz));

@@ -63,6 +63,22 @@ __device__ __forceinline__ double rsqrt64(double x) {
     return fma(0.5 * y, e, y);
 }
 
+// Softened monopole factors in FP64 for x = |d|^2 + eps^2 > 0: w3 = m x^(-3/2) and (POT)
+// mr = m x^(-1/2).  From the hardware estimate y of x^(-1/2) and its residual
+// e = 1 - x y^2, m y^3 (1 + 3e/2) and m y (1 + e/2) are the first-order corrections:
+// relative errors of about 7.5 and 1.5 times the square of the estimate's error, like
+// one Newton step on y, but with two dependent operations fewer before the sums.
+template <bool POT>
+__device__ __forceinline__ void mono64(double x, double m, double &w3, double &mr) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double y2 = y * y;
+    const double my = m * y;
+    const double e = fma(-x, y2, 1.0);
+    const double my3 = my * y2;
+    w3 = fma(1.5 * my3, e, my3);
+    if (POT) mr = fma(0.5 * my, e, my);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -405,9 +421,8 @@ struct Sums64 {
         const double dx = px - tx, dy = py - ty, dz = pz - tz;
         const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
         if (eps2 > 0.0 || r2 > 0.0) {
-            const double ri = rsqrt64(r2);
-            const double mr = pm * ri;
-            const double w3 = mr * ri * ri;
+            double w3, mr = 0.0;
+            mono64<POT>(r2, pm, w3, mr);
             ax = fma(w3, dx, ax);
             ay = fma(w3, dy, ay);
             az = fma(w3, dz, az);
