@@ -129,6 +129,36 @@ def test_theta_zero_is_direct_sum(ctx, prec):
     assert rel_rms(r["acc"].cpu().numpy(), d["acc"]) <= tol
 
 
+def test_fp64_pair_term_accuracy(ctx):
+    """FP64 pair terms against the closed form m d / |d|^3 for single pairs at separations over 40
+    binades (a forest of 256 two-body simulations, theta = 0, no softening).  The walk corrects
+    the force factor of the hardware reciprocal square root estimate y to first order in its
+    residual, m y^3 (1 + 3e/2) with e = 1 - x y^2, which leaves 7.5 times the square of the
+    estimate's relative error (below 2^-24, so about 2.7e-14) plus a few roundings; an error in
+    the correction would leave the estimate's own error, of order 1e-8."""
+    rng = np.random.default_rng(11)
+    K = 256
+    pos = np.zeros((2 * K, 3))
+    for s in range(K):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        pos[2 * s + 1] = d * np.ldexp(1.0 + rng.random(), -20 + (40 * s) // K)   # the other body at the origin
+    mass = np.tile([0.5, 0.25], K)
+    plist = [bh.params(0.0, 0.0, precision="fp64") for _ in range(K)]
+    forest = bh.Forest(ctx, [2] * K, plist, dev(pos), dev(np.zeros_like(pos)), dev(mass))
+    acc = forest.forces().cpu().numpy()
+    ctx.sync()
+    P = pos.astype(np.longdouble)
+    d = P[1::2] - P[0::2]
+    r2 = (d * d).sum(axis=1)
+    r3 = (r2 * np.sqrt(r2))[:, None]
+    ref = np.empty((2 * K, 3), dtype=np.longdouble)
+    ref[0::2] = 0.25 * d / r3
+    ref[1::2] = -0.5 * d / r3
+    err = np.sqrt(((acc - ref) ** 2).sum(axis=1)) / np.sqrt((ref ** 2).sum(axis=1))
+    assert float(err.max()) <= 5e-14
+
+
 def test_forces_plain_equals_stats_variant(ctx):
     s = icgen.plummer(4096, 1)
     for prec in ("fp64", "fp32"):
