@@ -462,47 +462,54 @@ def theta_two_spheres(a, bh, torch, stream):
 
 
 def leaf16(a, bh, torch, stream, pos0, vel0, mass, s):
-    """The headline configuration with leaves of up to 16 particles (FP32): step and walk
-    times, interactions per particle and the error against the oracle on sampled targets."""
+    """The headline configuration with leaves of up to 16 particles, FP32 (top level) and FP64
+    (`fp64`): step and walk times, interactions per particle and the error against the oracle's
+    leaf_cap-16 walk on sampled targets (one oracle reference for both precisions)."""
     import numpy as np
 
     import oracle
-    p = bh.params(a.theta, a.eps, 1.0, 16, "fp32")
-    sim = bh.Sim(ctx_of(bh, torch), pos0.clone(), vel0.clone(), mass, p)
-    sim.step(1, a.dt)
-    torch.cuda.synchronize()
-    e0, e1 = _events(torch)
-    steps = max(2, min(a.steps, 5))
-    e0.record(stream)
-    sim.step(steps, a.dt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / steps
-    tree = bh.Tree(sim.ctx, pos0, mass, p).upward()
-    st = tree.forces_stats()
-    w0, w1 = _events(torch)
-    w0.record(stream)
-    for _ in range(a.walk_reps):
-        tree.forces()
-    w1.record(stream)
-    torch.cuda.synchronize()
-    ms_walk = w0.elapsed_time(w1) / a.walk_reps
-    tot = st["totals"]
-    inter = tot["n_mono"] + tot["n_p2p"]
     rng = np.random.default_rng(1)
     ns = min(16384, a.n)
     tg = np.sort(rng.choice(a.n, ns, replace=False)).astype(np.int64)
     ref = oracle.Tree(s.pos, s.mass, 16).walk(a.theta, a.eps, 1.0, tg, nthreads=len(os.sched_getaffinity(0)))
-    rms, mx = _errors(st["acc"].cpu().numpy()[tg], ref["acc"])
-    sets_equal = bool(np.array_equal(st["n_mono"].cpu().numpy()[tg], ref["n_mono"]) and
-                      np.array_equal(st["hash"].cpu().numpy().view(np.uint64)[tg], ref["hash"]))
-    out = {"leaf_cap": 16, "precision": "fp32", "ms_per_step": ms_step, "value": a.n / (ms_step * 1e-3) / 1e6,
-           "walk_ms": ms_walk, "interactions_per_particle": inter / a.n,
-           "walk_tflops": FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / 1e12,
-           "force_error_vs_oracle": {"rms_rel": rms, "max_rel": mx, "interaction_sets_equal": sets_equal,
-                                     "sample": f"{ns} random targets at the initial positions"}}
-    print(f"# leaf_cap 16: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, {inter / a.n:.1f} interactions/particle, "
-          f"rms {rms:.2e}", file=sys.stderr, flush=True)
+
+    def leg(prec):
+        p = bh.params(a.theta, a.eps, 1.0, 16, prec)
+        sim = bh.Sim(ctx_of(bh, torch), pos0.clone(), vel0.clone(), mass, p)
+        sim.step(1, a.dt)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        steps = max(2, min(a.steps, 5))
+        e0.record(stream)
+        sim.step(steps, a.dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / steps
+        tree = bh.Tree(sim.ctx, pos0, mass, p).upward()
+        st = tree.forces_stats()
+        w0, w1 = _events(torch)
+        w0.record(stream)
+        for _ in range(a.walk_reps):
+            tree.forces()
+        w1.record(stream)
+        torch.cuda.synchronize()
+        ms_walk = w0.elapsed_time(w1) / a.walk_reps
+        tot = st["totals"]
+        inter = tot["n_mono"] + tot["n_p2p"]
+        rms, mx = _errors(st["acc"].cpu().numpy()[tg], ref["acc"])
+        sets_equal = bool(np.array_equal(st["n_mono"].cpu().numpy()[tg], ref["n_mono"]) and
+                          np.array_equal(st["hash"].cpu().numpy().view(np.uint64)[tg], ref["hash"]))
+        print(f"# leaf_cap 16 {prec}: step {ms_step:.3f} ms, walk {ms_walk:.3f} ms, {inter / a.n:.1f} "
+              f"interactions/particle, rms {rms:.2e}", file=sys.stderr, flush=True)
+        return {"ms_per_step": ms_step, "value": a.n / (ms_step * 1e-3) / 1e6,
+                "walk_ms": ms_walk, "interactions_per_particle": inter / a.n,
+                "walk_tflops": FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / 1e12,
+                "force_error_vs_oracle": {"rms_rel": rms, "max_rel": mx, "interaction_sets_equal": sets_equal,
+                                          "sample": f"{ns} random targets at the initial positions"}}
+
+    out = {"leaf_cap": 16, "precision": "fp32"}
+    out.update(leg("fp32"))
+    out["fp64"] = dict(precision="fp64", **leg("fp64"))
     return out
 
 
